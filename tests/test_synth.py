@@ -1,0 +1,58 @@
+"""The seeded generator: splitmix64 reference values, canonical uniform elements, shapes."""
+import numpy as np
+
+import gkr_synth as gs
+
+
+def test_splitmix64_reference_outputs():
+    # splitmix64 with state 0: published first outputs of the reference generator
+    assert [int(v) for v in gs.stream(0, 3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    assert gs.stream_at(0, 2) == 0x06C45D188009454F
+    assert [int(v) for v in gs.stream(12345, 4, start=2)] == [int(v) for v in gs.stream(12345, 6)[2:]]
+
+
+def test_elements_are_canonical_and_slices_agree():
+    key = gs.stream_key(9, gs.PURPOSE_INPUT)
+    full = gs.field_elements(key, 3000)
+    vals = gs.elements_to_ints(full)
+    assert all(0 <= v < gs.MODULUS for v in vals)
+    assert len(set(vals)) == len(vals)
+    part = gs.field_elements(key, 100, start=1234)
+    assert np.array_equal(part, full[1234:1334])
+    assert gs.elements_to_ints(gs.ints_to_elements(vals[:50])) == vals[:50]
+    # roughly uniform: the top limb spreads over [0, top limb of the modulus]
+    top = full[:, 7].astype(np.float64) / (gs.MODULUS >> 224)
+    assert 0.45 < top.mean() < 0.55
+
+
+def test_wiring_ranges_and_mul_fraction():
+    spec = gs.CircuitSpec(depth=3, log_copies=2, log_sub_width=(12, 5, 12, 3), mu=(3, 10), seed=4)
+    w = gs.make_wiring(spec)
+    for i, layer in enumerate(w):
+        assert layer.x.shape == (1 << spec.log_sub_width[i],)
+        assert layer.x.max() < 1 << spec.log_sub_width[i + 1]
+        assert layer.y.max() < 1 << spec.log_sub_width[i + 1]
+        assert set(np.unique(layer.kind)) <= {gs.GATE_ADD, gs.GATE_MUL}
+    assert abs(w[0].kind.mean() - 0.3) < 0.03
+    assert abs(w[2].kind.mean() - 0.3) < 0.03
+    # deterministic
+    w2 = gs.make_wiring(spec)
+    assert all(np.array_equal(a.x, b.x) and np.array_equal(a.kind, b.kind) for a, b in zip(w, w2))
+
+
+def test_workload_shapes():
+    c1, c2, c3 = gs.plain_c1(), gs.data_parallel_c2(), gs.worker_share_c3()
+    assert c1.log_width(0) == 10 and c1.depth == 4 and c1.log_copies == 0
+    assert c2.log_width(0) == 20 and c2.log_copies == 8 and c2.depth == 16
+    assert c3.log_width(0) == 26 and c3.log_copies == 12 and c3.depth == 24 and c3.mu == (3, 10)
+    jobs = gs.batch_jobs_c4()
+    assert len(jobs) == 64
+    for j in jobs:
+        s = j.log_width(0)
+        assert 10 <= s <= 18 and 8 <= j.depth <= 32 and 4 <= j.log_copies <= min(10, s - 4)
+    srv = gs.serving_jobs_c5()
+    assert len(srv) == 256
+    for j in srv:
+        assert 12 <= j.log_width(0) <= 22 and 8 <= j.depth <= 24
+    gaps = gs.poisson_gaps(10000, rate=4.0)
+    assert abs(gaps.mean() - 0.25) < 0.02 and gaps.min() >= 0
