@@ -1,0 +1,175 @@
+/*
+ * gkr.h - C ABI of the MI355X data-parallel GKR prover.
+ *
+ * The library proves that `outputs = C(inputs)` for a layered arithmetic
+ * circuit C made of 2^n identical copies of one sub-circuit of fan-in-2 ADD
+ * and MUL gates, over the BN254 scalar field. Layer 0 is the output layer and
+ * layer d the input layer; gate layer i reads layer i+1 (GKR section of the
+ * paper: the layer relation V_i(g) = sum add_i(g,x,y)(V(x)+V(y)) +
+ * mult_i(g,x,y) V(x)V(y)). Each layer is reduced with the two-phase
+ * linear-time product sumcheck (Libra section) over bookkeeping tables; the
+ * copy bits are bound after the sub-circuit bits, the order of the
+ * distributed multilinear-product sumcheck (Section 3.2.1) on one worker.
+ *
+ * Conventions shared by every entry point
+ *   - Field elements at the boundary are gkr_fr: the canonical value (< p)
+ *     as 8 little-endian 32-bit limbs. Montgomery form never crosses the ABI.
+ *   - Gate g = z * 2^n + c is gate z of copy c (copy index in the low bits).
+ *     A gate of layer i reads gates x*2^n + c and y*2^n + c of layer i+1.
+ *   - Points are given with variable 1 first; variable 1 is the most
+ *     significant index bit, so the sub-circuit bits come before the copy bits.
+ *   - Pointers named d_* are device pointers (memory from hipMalloc or a torch
+ *     CUDA tensor); all other pointers are host pointers. The caller owns every
+ *     buffer; the library never frees caller memory and keeps no pointer to a
+ *     caller buffer after a call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is queued asynchronously on that stream; the host
+ *     returns as soon as it is queued. No entry point allocates device memory
+ *     while proving, synchronises the stream or copies between host and
+ *     device, so a whole proof can be captured in a HIP graph.
+ *   - Every entry point returns GKR_OK (0) or a negative status; on failure
+ *     gkr_last_error() returns a message for the calling thread. No C++
+ *     exception crosses the ABI. Entry points that fail leave caller buffers
+ *     unspecified but never write outside them.
+ *
+ * Fiat-Shamir transcript (non-interactive form of the verifier's challenges):
+ *   init           st = SHA256("SISU-GKR-v1" || LE64(seed))
+ *   absorb(t, m)   st = SHA256(st || t || m), t a four-byte tag
+ *   squeeze        repeat st = SHA256(st || "GKRC"); v = LE(st) mod 2^254 until v < p
+ * Statement: absorb("GKRD", circuit digest), absorb("GKRD", tree digest of the
+ * inputs), absorb("GKRD", tree digest of the outputs). Round messages are
+ * absorbed with "GKRR" (e0 || e1 || e2), a phase's final value with "GKRV".
+ *
+ * Proof layout: for each gate layer i = 0..d-1 with s' = s_{i+1}:
+ *   s' phase-1 messages (e0, e1, e2: the round polynomial at t = 0, 1, 2),
+ *   vx, s' phase-2 messages, vy  -- (6 s' + 2) * 32 bytes, canonical elements.
+ */
+#ifndef GKR_H
+#define GKR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GKR_OK 0
+#define GKR_EINVAL (-1)       /* bad argument, shape or buffer size          */
+#define GKR_ENOMEM (-2)       /* host or device allocation failed            */
+#define GKR_EDEVICE (-3)      /* a HIP call or kernel launch failed          */
+#define GKR_EBUFSZ (-4)       /* an output or workspace buffer is too small  */
+#define GKR_EUNSUPPORTED (-5) /* shape beyond the supported limits           */
+
+#define GKR_GATE_ADD 0u
+#define GKR_GATE_MUL 1u
+
+/* Largest supported log2 layer width s_i = sigma_i + n, and copy count n. */
+#define GKR_MAX_LOG_WIDTH 30u
+#define GKR_MAX_LOG_COPIES 24u
+#define GKR_MAX_DEPTH 4096u
+
+typedef struct {
+  uint32_t limb[8];
+} gkr_fr;
+
+/* One gate of a sub-circuit: inputs x, y index the next layer of the same
+ * copy; type is GKR_GATE_ADD or GKR_GATE_MUL. */
+typedef struct {
+  uint32_t x, y, type;
+} gkr_gate;
+
+typedef struct gkr_circuit gkr_circuit;
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* gkr_last_error(void);
+
+/*
+ * Create a circuit: `depth` gate layers (1..GKR_MAX_DEPTH), 2^log_copies
+ * copies, log_sub_width[0..depth] = sigma_i (layer 0 = output, [depth] =
+ * input), gates[i] = 2^{sigma_i} gates of layer i's sub-circuit (host memory,
+ * copied). Validates every index, builds the wiring indexes by x and by y,
+ * uploads them to the current device and computes the circuit digest. The
+ * circuit is immutable and may be used from several streams at once. When no
+ * HIP device is present the circuit is created host-only: gkr_verify works
+ * and every proving call returns GKR_EDEVICE.
+ * Errors: GKR_EINVAL (bad shape or gate), GKR_EUNSUPPORTED (too large),
+ * GKR_ENOMEM, GKR_EDEVICE.
+ */
+int32_t gkr_circuit_create(uint32_t depth, uint32_t log_copies, const uint32_t* log_sub_width,
+                           const gkr_gate* const* gates, gkr_circuit** out);
+void gkr_circuit_destroy(gkr_circuit* circuit);
+
+/* Device workspace one proof needs (layer store + bookkeeping tables + state). */
+size_t gkr_workspace_bytes(const gkr_circuit* circuit);
+/* Bytes of a whole proof, and of gate layer `layer`'s part: (6 s_{layer+1} + 2) * 32. */
+size_t gkr_proof_bytes(const gkr_circuit* circuit);
+size_t gkr_layer_proof_bytes(const gkr_circuit* circuit, uint32_t layer);
+/* Field-gate count of one proof: sum over gate layers of 2^{s_i}. */
+uint64_t gkr_gate_layers(const gkr_circuit* circuit);
+
+/*
+ * Whole proof (forward evaluation, statement binding, output claim, every
+ * layer). d_inputs: 2^{s_d} canonical inputs. Writes d_outputs (2^{s_0}
+ * elements) and the proof into d_proof (device, proof_cap bytes);
+ * *proof_len (host) receives gkr_proof_bytes(). d_ws: gkr_workspace_bytes()
+ * bytes of device memory owned by this call until the stream reaches its end;
+ * concurrent proofs need separate workspaces.
+ * Inputs must be canonical (< p); non-canonical inputs give an unspecified
+ * (but in-bounds) result. Errors: GKR_EINVAL, GKR_EBUFSZ (proof_cap or
+ * ws_bytes too small), GKR_EDEVICE.
+ */
+int32_t gkr_prove_circuit(const gkr_circuit* circuit, const gkr_fr* d_inputs, uint64_t seed,
+                          gkr_fr* d_outputs, uint8_t* d_proof, size_t proof_cap, size_t* proof_len,
+                          void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * Bind the statement: d_state (32 bytes, device) receives the transcript state
+ * after init(seed) and the three "GKRD" absorbs. d_inputs / d_outputs are the
+ * canonical input (2^{s_d}) and output (2^{s_0}) vectors.
+ */
+int32_t gkr_transcript_init(const gkr_circuit* circuit, uint64_t seed, const gkr_fr* d_inputs,
+                            const gkr_fr* d_outputs, uint8_t* d_state, void* d_ws, size_t ws_bytes,
+                            void* stream);
+
+/*
+ * Output claim: squeezes g (s_0 challenges) from d_state (updated in place)
+ * and evaluates the output MLE there. Writes d_g (s_0 elements, variable 1
+ * first) and d_claim (1 element) = V_0~(g).
+ */
+int32_t gkr_output_claim(const gkr_circuit* circuit, const gkr_fr* d_outputs, uint8_t* d_state,
+                         gkr_fr* d_g, gkr_fr* d_claim, void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * One gate layer: reduces claims about V_layer~ to claims about V_{layer+1}~.
+ *   d_next      V_{layer+1}, 2^{s_{layer+1}} canonical elements
+ *   d_u, d_v    points (s_layer elements each); d_v is ignored for layer 0
+ *   d_claim_u/v claimed values V_layer~(u), V_layer~(v); d_claim_v ignored for layer 0
+ *   d_state     transcript state (32 bytes), read then updated in place. For
+ *               layer 0 it is the state after the output point was squeezed;
+ *               for later layers, after the previous layer's last absorb.
+ * For layer > 0 the call squeezes alpha, beta and proves alpha*V~(u) + beta*V~(v);
+ * layer 0 proves V~(u). Outputs: d_rx, d_ry (s_{layer+1} elements each),
+ * d_vx = V_{layer+1}~(rx), d_vy = V_{layer+1}~(ry), and the layer's proof
+ * bytes into d_layer_proof (gkr_layer_proof_bytes()). The claims must be the
+ * true MLE values: the prover derives e1 of each round from the running claim.
+ */
+int32_t gkr_prove_layer(const gkr_circuit* circuit, uint32_t layer, const gkr_fr* d_next,
+                        const gkr_fr* d_u, const gkr_fr* d_v, const gkr_fr* d_claim_u,
+                        const gkr_fr* d_claim_v, uint8_t* d_state, gkr_fr* d_rx, gkr_fr* d_ry,
+                        gkr_fr* d_vx, gkr_fr* d_vy, uint8_t* d_layer_proof, void* d_ws,
+                        size_t ws_bytes, void* stream);
+
+/*
+ * Verifier (host only, synchronous). inputs / outputs / proof are host
+ * buffers. Returns 1 (accept), 0 (reject) or a negative status for malformed
+ * arguments: GKR_EINVAL for a proof of the wrong length or any element >= p.
+ */
+int32_t gkr_verify(const gkr_circuit* circuit, const gkr_fr* inputs, const gkr_fr* outputs,
+                   uint64_t seed, const uint8_t* proof, size_t proof_len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GKR_H */

@@ -5,12 +5,13 @@ message (Section 3.2.1). Here the challenges are derived from a SHA-256 hash
 chain so a proof is a deterministic byte string:
 
   init           st = SHA256("SISU-GKR-v1" || LE64(seed))
-  absorb(t, m)   st = SHA256(st || t || m), t a one-byte tag
-  squeeze        repeat st = SHA256(st || "C"); v = LE(st) mod 2^254  until v < p
+  absorb(t, m)   st = SHA256(st || t || m), t a four-byte tag
+  squeeze        repeat st = SHA256(st || "GKRC"); v = LE(st) mod 2^254  until v < p
 
-Tags: "D" statement digests, "R" a round message (e0 || e1 || e2), "V" a
-layer's final value. Field elements are absorbed as canonical 32-byte
-little-endian strings.
+Tags: "GKRD" statement digests, "GKRR" a round message (e0 || e1 || e2),
+"GKRV" a layer's final value. Tags are four bytes so that every absorbed
+message stays word-aligned for SHA-256. Field elements are absorbed as
+canonical 32-byte little-endian strings.
 
 Statement digests (absorbed before any challenge):
   circuit  SHA256(LE32 d || LE32 n || LE32 sigma_0..sigma_d ||
@@ -27,10 +28,10 @@ from .field import P, encode_all, to_bytes
 
 DOMAIN = b"SISU-GKR-v1"
 CHUNK_BYTES = 8192
-TAG_DIGEST = b"D"
-TAG_ROUND = b"R"
-TAG_VALUE = b"V"
-TAG_CHALLENGE = b"C"
+TAG_DIGEST = b"GKRD"
+TAG_ROUND = b"GKRR"
+TAG_VALUE = b"GKRV"
+TAG_CHALLENGE = b"GKRC"
 _MASK254 = (1 << 254) - 1
 
 

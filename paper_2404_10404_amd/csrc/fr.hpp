@@ -1,0 +1,195 @@
+// BN254 scalar-field arithmetic for gfx950 and the host.
+//
+// The paper proves over BN254 (Section 4.1, choice of finite field). Elements
+// live in Montgomery form x*R mod p with R = 2^256, as eight 32-bit limbs
+// (little-endian). Products use coarsely integrated operand scanning (CIOS)
+// Montgomery multiplication: 32x32->64 multiply-adds on the VALU (the work is
+// a carry chain, not a dense float contraction, so MFMA does not apply).
+// p < 2^254, so sums of two reduced values never overflow 256 bits and a
+// CIOS result is below 2p before its final conditional subtraction.
+#pragma once
+
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define GKR_HD __host__ __device__ inline __attribute__((always_inline))
+#else
+#define GKR_HD inline
+#endif
+
+namespace gkr {
+
+struct Fr {
+  uint32_t v[8];
+};
+
+// p = 0x30644e72e131a029b85045b68181585d2833e84879b9709143e1f593f0000001
+#define GKR_P0 0xf0000001u
+#define GKR_P1 0x43e1f593u
+#define GKR_P2 0x79b97091u
+#define GKR_P3 0x2833e848u
+#define GKR_P4 0x8181585du
+#define GKR_P5 0xb85045b6u
+#define GKR_P6 0xe131a029u
+#define GKR_P7 0x30644e72u
+#define GKR_NINV 0xefffffffu  // -p^{-1} mod 2^32
+
+GKR_HD uint32_t p_limb(int k) {
+  switch (k) {
+    case 0: return GKR_P0;
+    case 1: return GKR_P1;
+    case 2: return GKR_P2;
+    case 3: return GKR_P3;
+    case 4: return GKR_P4;
+    case 5: return GKR_P5;
+    case 6: return GKR_P6;
+    default: return GKR_P7;
+  }
+}
+
+GKR_HD Fr fr_make(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t a4, uint32_t a5,
+                  uint32_t a6, uint32_t a7) {
+  Fr r;
+  r.v[0] = a0; r.v[1] = a1; r.v[2] = a2; r.v[3] = a3;
+  r.v[4] = a4; r.v[5] = a5; r.v[6] = a6; r.v[7] = a7;
+  return r;
+}
+
+GKR_HD Fr fr_zero() { return fr_make(0, 0, 0, 0, 0, 0, 0, 0); }
+// R mod p: the Montgomery form of 1.
+GKR_HD Fr fr_one() {
+  return fr_make(0x4ffffffbu, 0xac96341cu, 0x9f60cd29u, 0x36fc7695u, 0x7879462eu, 0x666ea36fu,
+                 0x9a07df2fu, 0x0e0a77c1u);
+}
+// R^2 mod p: multiplying a canonical value by it converts to Montgomery form.
+GKR_HD Fr fr_r2() {
+  return fr_make(0xae216da7u, 0x1bb8e645u, 0xe35c59e3u, 0x53fe3ab1u, 0x53bb8085u, 0x8c49833du,
+                 0x7f4e44a5u, 0x0216d0b1u);
+}
+// Montgomery form of 1/2.
+GKR_HD Fr fr_inv2() {
+  return fr_make(0x1ffffffeu, 0x783c14d8u, 0x0c8d1eddu, 0xaf982f6fu, 0xfcfd4f45u, 0x8f5f7492u,
+                 0x3d9cbfacu, 0x1f37631au);
+}
+
+// a - p if a >= p, else a (a < 2p).
+GKR_HD Fr fr_reduce_once(const Fr& a) {
+  Fr t;
+  uint64_t br = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    uint64_t d = (uint64_t)a.v[k] - p_limb(k) - br;
+    t.v[k] = (uint32_t)d;
+    br = d >> 63;
+  }
+  return br ? a : t;
+}
+
+GKR_HD Fr fr_add(const Fr& a, const Fr& b) {
+  Fr s;
+  uint64_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    uint64_t x = (uint64_t)a.v[k] + b.v[k] + c;
+    s.v[k] = (uint32_t)x;
+    c = x >> 32;
+  }
+  return fr_reduce_once(s);
+}
+
+GKR_HD Fr fr_sub(const Fr& a, const Fr& b) {
+  Fr d;
+  uint64_t br = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    uint64_t x = (uint64_t)a.v[k] - b.v[k] - br;
+    d.v[k] = (uint32_t)x;
+    br = x >> 63;
+  }
+  if (br) {
+    uint64_t c = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      uint64_t x = (uint64_t)d.v[k] + p_limb(k) + c;
+      d.v[k] = (uint32_t)x;
+      c = x >> 32;
+    }
+  }
+  return d;
+}
+
+GKR_HD Fr fr_neg(const Fr& a) { return fr_sub(fr_zero(), a); }
+GKR_HD Fr fr_double(const Fr& a) { return fr_add(a, a); }
+
+// Montgomery product a*b*R^{-1} mod p (CIOS, 8 x 32-bit limbs).
+GKR_HD Fr fr_mul(const Fr& a, const Fr& b) {
+  uint32_t t[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) t[k] = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    uint64_t c = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      uint64_t s = (uint64_t)a.v[j] * b.v[i] + t[j] + c;
+      t[j] = (uint32_t)s;
+      c = s >> 32;
+    }
+    uint64_t s8 = (uint64_t)t[8] + c;
+    t[8] = (uint32_t)s8;
+    t[9] = (uint32_t)(s8 >> 32);
+    uint32_t m = t[0] * GKR_NINV;
+    uint64_t s = (uint64_t)m * GKR_P0 + t[0];
+    c = s >> 32;
+#pragma unroll
+    for (int j = 1; j < 8; ++j) {
+      s = (uint64_t)m * p_limb(j) + t[j] + c;
+      t[j - 1] = (uint32_t)s;
+      c = s >> 32;
+    }
+    s = (uint64_t)t[8] + c;
+    t[7] = (uint32_t)s;
+    t[8] = t[9] + (uint32_t)(s >> 32);
+  }
+  Fr r;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) r.v[k] = t[k];
+  return fr_reduce_once(r);
+}
+
+GKR_HD Fr fr_sqr(const Fr& a) { return fr_mul(a, a); }
+GKR_HD Fr fr_to_mont(const Fr& a) { return fr_mul(a, fr_r2()); }
+GKR_HD Fr fr_from_mont(const Fr& a) { return fr_mul(a, fr_make(1, 0, 0, 0, 0, 0, 0, 0)); }
+
+GKR_HD bool fr_eq(const Fr& a, const Fr& b) {
+  uint32_t d = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) d |= a.v[k] ^ b.v[k];
+  return d == 0;
+}
+
+// True when the limbs hold a value below p.
+GKR_HD bool fr_is_canonical(const Fr& a) {
+  uint64_t br = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    uint64_t d = (uint64_t)a.v[k] - p_limb(k) - br;
+    br = d >> 63;
+  }
+  return br != 0;
+}
+
+// 1 - a (both Montgomery).
+GKR_HD Fr fr_one_minus(const Fr& a) { return fr_sub(fr_one(), a); }
+
+// Value at r of the degree-2 polynomial with values e0, e1, e2 at t = 0, 1, 2:
+// g(r) = e0 + r (e1 - e0) + r (r - 1) / 2 * (e2 - 2 e1 + e0).
+GKR_HD Fr fr_interp3(const Fr& e0, const Fr& e1, const Fr& e2, const Fr& r) {
+  Fr d1 = fr_sub(e1, e0);
+  Fr d2 = fr_add(fr_sub(e2, fr_double(e1)), e0);
+  Fr rr = fr_mul(fr_mul(r, fr_sub(r, fr_one())), fr_inv2());
+  return fr_add(fr_add(e0, fr_mul(r, d1)), fr_mul(rr, d2));
+}
+
+}  // namespace gkr

@@ -1,0 +1,108 @@
+// Internal declarations shared by the device kernels, the host driver and the
+// host verifier of the GKR prover library.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/gkr.h"
+#include "fr.hpp"
+#include "sha256.hpp"
+
+namespace gkr {
+
+constexpr int kBlock = 256;             // threads per workgroup for every kernel
+constexpr uint32_t kMaxRoundBlocks = 4096;  // cap on workgroups of a reduction launch
+constexpr int kMaxPartialValues = 2;    // reduced values per workgroup
+constexpr uint32_t kChunkWords = 2048;  // 8 KiB SHA-256 leaf chunk of a tree digest
+
+// Transcript tags as big-endian words ("GKRD", "GKRR", "GKRV", "GKRC").
+constexpr uint32_t kTagDigest = 0x474B5244u;
+constexpr uint32_t kTagRound = 0x474B5252u;
+constexpr uint32_t kTagValue = 0x474B5256u;
+constexpr uint32_t kTagChallenge = 0x474B5243u;
+
+// Gate-layer wiring on the device. Gate records pack the type into bit 31.
+struct LayerWiring {
+  const uint2* gates;   // [2^{sigma_i}]      .x = x | type<<31, .y = y
+  const uint32_t* xrow; // [2^{sigma_{i+1}}+1] CSR of gates by x
+  const uint2* xent;    // [2^{sigma_i}]      .x = z, .y = y | type<<31
+  const uint32_t* yrow; // [2^{sigma_{i+1}}+1] CSR of gates by y
+  const uint2* yent;    // [2^{sigma_i}]      .x = z, .y = x | type<<31
+};
+
+// Scalars of one proof in device memory (all field values in Montgomery form).
+struct DevState {
+  uint32_t st[8];   // transcript chaining value, SHA-256 words h[0..7]
+  uint32_t counter; // last-workgroup counter of grid reductions (returns to 0)
+  uint32_t pad[7];
+  Fr claim;         // running sumcheck claim
+  Fr alpha, beta;
+  Fr vx, vy;
+  Fr su, sv;        // sum_c U[c], sum_c V[c]
+  Fr ka_f, kb_f;    // Ka~, Kb~ at the phase-2 local point
+  Fr scratch[4];
+};
+
+// Tunables of the round schedule (autotuned; see gkr_tuning.*).
+struct Tuning {
+  uint32_t tail_log;        // single-workgroup tail once a table has <= 2^tail_log entries
+  uint32_t max_round_blocks;
+};
+
+// Device buffers of one proof, carved out of the caller's workspace.
+struct Workspace {
+  Fr* layer[GKR_MAX_DEPTH + 1];  // only [0..d] used
+  Fr *G, *H, *Wf;
+  Fr *aU, *bV, *Cu, *Cv, *U, *V, *EC, *EL, *EqR;
+  Fr *P, *Q, *Fa, *Fb, *Ks, *Ka, *Kb;
+  Fr *Wc, *Fc, *Kc, *wpart;
+  Fr* partials;
+  uint32_t *dig_a, *dig_b;  // tree-digest levels (8 words per digest)
+  uint32_t* dig_in;         // final digests (8 words each)
+  uint32_t* dig_out;
+  Fr* chal;                 // g, then rx/ry of every layer
+  DevState* state;
+  size_t bytes;
+};
+
+// Host-side description of the workspace layout of a circuit.
+struct Plan {
+  size_t off_layer[GKR_MAX_DEPTH + 1];
+  size_t off_G, off_H, off_Wf, off_aU, off_bV, off_Cu, off_Cv, off_U, off_V, off_EC, off_EL,
+      off_EqR, off_P, off_Q, off_Fa, off_Fb, off_Ks, off_Ka, off_Kb, off_Wc, off_Fc, off_Kc,
+      off_wpart, off_partials, off_dig_a, off_dig_b, off_dig_in, off_dig_out, off_chal, off_state;
+  size_t total;
+  uint32_t ychunks;  // y-range split of the phase-2 copy-table pass
+  size_t dig_level_words;
+};
+
+}  // namespace gkr
+
+struct gkr_circuit {
+  uint32_t depth = 0, n = 0;
+  std::vector<uint32_t> sigma;                // [depth+1]
+  std::vector<std::vector<gkr_gate>> gates;   // host copy of each layer's sub-circuit
+  uint32_t digest[8];                         // circuit digest, SHA-256 words
+  int device = 0;
+  void* dev_block = nullptr;
+  std::vector<gkr::LayerWiring> wiring;       // device pointers into dev_block
+  gkr::Plan plan;
+  uint32_t s(uint32_t i) const { return sigma[i] + n; }
+};
+
+namespace gkr {
+
+void set_error(const std::string& msg);
+size_t plan_workspace(const gkr_circuit& c, Plan& p);
+Workspace bind_workspace(const gkr_circuit& c, void* base);
+uint32_t host_chal_index_rx(const gkr_circuit& c, uint32_t layer);  // index of rx[0] of a layer in chal
+uint32_t host_chal_index_ry(const gkr_circuit& c, uint32_t layer);
+
+// Host SHA-256 of a byte string (used for the transcript seed and the circuit digest).
+void sha256_bytes(const uint8_t* data, size_t len, uint32_t out_words[8]);
+
+}  // namespace gkr

@@ -1,0 +1,24 @@
+// Round-schedule tunables. Proofs read one consistent snapshot when they are
+// queued; changing the tuning never changes proof bytes, only launch shapes.
+#include <atomic>
+
+#include "gkr_tuning.hpp"
+
+namespace gkr {
+
+static std::atomic<uint32_t> g_tail_log{10};
+static std::atomic<uint32_t> g_max_round_blocks{2048};
+
+Tuning current_tuning() {
+  Tuning t;
+  t.tail_log = g_tail_log.load(std::memory_order_relaxed);
+  t.max_round_blocks = g_max_round_blocks.load(std::memory_order_relaxed);
+  return t;
+}
+
+void store_tuning(const Tuning& t) {
+  g_tail_log.store(t.tail_log, std::memory_order_relaxed);
+  g_max_round_blocks.store(t.max_round_blocks, std::memory_order_relaxed);
+}
+
+}  // namespace gkr

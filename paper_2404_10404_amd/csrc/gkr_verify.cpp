@@ -1,0 +1,264 @@
+// Host verifier of the GKR proofs (synchronous, no device work).
+//
+// Replays the transcript, checks g_j(0) + g_j(1) = claim for every round
+// (Section 3.2.1), checks each layer's final claim against the wiring
+// predicates, and finally evaluates the input MLE at both points itself.
+//
+// The predicates use the data-parallel structure: with
+// T[z,c] = alpha eq(u,(z,c)) + beta eq(v,(z,c)),
+//   mult~(rx, ry) = sum_{MUL z} sum_c T[z,c] eq(rx,(x_z,c)) eq(ry,(y_z,c))
+//                 = sum_{MUL z} (alpha eqL(u,z) Cu + beta eqL(v,z) Cv) eqL(rx,x_z) eqL(ry,y_z)
+// where Cu = prod_k (u_k rx_k ry_k + (1-u_k)(1-rx_k)(1-ry_k)) over the copy
+// variables (and Cv likewise), so a layer costs O(2^sigma + n).
+#include <string.h>
+
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "gkr_internal.hpp"
+
+namespace gkr {
+namespace {
+
+Fr to_m(const Fr& a) { return fr_to_mont(a); }
+Fr from_m(const Fr& a) { return fr_from_mont(a); }
+
+std::vector<Fr> eq_table_host(const Fr* r, uint32_t k) {
+  std::vector<Fr> t(1ull << k);
+  t[0] = fr_one();
+  for (uint32_t i = 0; i < k; ++i) {
+    // append variable i as the new least significant bit
+    const uint64_t cur = 1ull << i;
+    const Fr ri = r[i], ni = fr_one_minus(r[i]);
+    for (uint64_t b = cur; b-- > 0;) {
+      const Fr v = t[b];
+      t[2 * b + 1] = fr_mul(v, ri);
+      t[2 * b] = fr_mul(v, ni);
+    }
+  }
+  return t;
+}
+
+// V~(r) for V given as canonical host limbs (converted on the fly), by folding.
+Fr mle_host(const gkr_fr* V, uint32_t k, const Fr* r) {
+  const uint64_t size = 1ull << k;
+  if (k == 0) return to_m(*reinterpret_cast<const Fr*>(&V[0]));
+  // first fold reads the canonical vector; parallel over a few threads for big inputs
+  std::vector<Fr> cur(size / 2);
+  const uint64_t half = size / 2;
+  const Fr r0 = r[0];
+  unsigned nt = std::thread::hardware_concurrency();
+  if (nt == 0) nt = 1;
+  if (half < (1u << 16)) nt = 1;
+  if (nt > 16) nt = 16;
+  auto fold_first = [&](uint64_t b0, uint64_t b1) {
+    for (uint64_t b = b0; b < b1; ++b) {
+      const Fr a = to_m(*reinterpret_cast<const Fr*>(&V[b]));
+      const Fr c = to_m(*reinterpret_cast<const Fr*>(&V[b + half]));
+      cur[b] = fr_add(a, fr_mul(r0, fr_sub(c, a)));
+    }
+  };
+  auto fold_next = [&](std::vector<Fr>& x, uint64_t h, const Fr& rj, uint64_t b0, uint64_t b1) {
+    for (uint64_t b = b0; b < b1; ++b) x[b] = fr_add(x[b], fr_mul(rj, fr_sub(x[b + h], x[b])));
+  };
+  auto parallel = [&](uint64_t n, auto&& fn) {
+    if (nt == 1 || n < (1u << 14)) {
+      fn(0, n);
+      return;
+    }
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t) th.emplace_back(fn, n * t / nt, n * (t + 1) / nt);
+    for (auto& t : th) t.join();
+  };
+  parallel(half, fold_first);
+  uint64_t m = half;
+  for (uint32_t j = 1; j < k; ++j) {
+    const uint64_t h = m / 2;
+    const Fr rj = r[j];
+    parallel(h, [&](uint64_t b0, uint64_t b1) { fold_next(cur, h, rj, b0, b1); });
+    m = h;
+  }
+  return cur[0];
+}
+
+// Tree digest of canonical elements (same structure as the device kernels).
+void tree_digest_host(const uint8_t* data, uint64_t nbytes, uint32_t out[8]) {
+  const uint64_t chunk = (uint64_t)kChunkWords * 4;
+  if (nbytes <= chunk) {
+    sha256_bytes(data, nbytes, out);
+    return;
+  }
+  const uint64_t nchunks = (nbytes + chunk - 1) / chunk;
+  std::vector<uint8_t> level(nchunks * 32);
+  for (uint64_t t = 0; t < nchunks; ++t) {
+    const uint64_t b = t * chunk, e = (b + chunk < nbytes) ? b + chunk : nbytes;
+    uint32_t h[8];
+    sha256_bytes(data + b, e - b, h);
+    for (int k = 0; k < 8; ++k) {
+      level[32 * t + 4 * k + 0] = (uint8_t)(h[k] >> 24);
+      level[32 * t + 4 * k + 1] = (uint8_t)(h[k] >> 16);
+      level[32 * t + 4 * k + 2] = (uint8_t)(h[k] >> 8);
+      level[32 * t + 4 * k + 3] = (uint8_t)h[k];
+    }
+  }
+  tree_digest_host(level.data(), level.size(), out);
+}
+
+struct HostTranscript {
+  Sha256State st;
+
+  void absorb_words(uint32_t tag, const uint32_t* words, int nw) {
+    std::vector<uint8_t> m;
+    auto put = [&](uint32_t w) {
+      m.push_back((uint8_t)(w >> 24));
+      m.push_back((uint8_t)(w >> 16));
+      m.push_back((uint8_t)(w >> 8));
+      m.push_back((uint8_t)w);
+    };
+    for (int k = 0; k < 8; ++k) put(st.h[k]);
+    put(tag);
+    for (int k = 0; k < nw; ++k) put(words[k]);
+    sha256_bytes(m.data(), m.size(), st.h);
+  }
+  void absorb_elements(uint32_t tag, const Fr* canon, int count) {
+    std::vector<uint32_t> w;
+    for (int i = 0; i < count; ++i)
+      for (int k = 0; k < 8; ++k) w.push_back(bswap32(canon[i].v[k]));
+    absorb_words(tag, w.data(), (int)w.size());
+  }
+  Fr squeeze() {  // canonical
+    for (;;) {
+      absorb_words(kTagChallenge, nullptr, 0);
+      Fr c = sha256_to_candidate(st);
+      if (fr_is_canonical(c)) return c;
+    }
+  }
+};
+
+Fr triple_eq(const Fr* a, const Fr* b, const Fr* c, uint32_t k) {
+  Fr acc = fr_one();
+  for (uint32_t i = 0; i < k; ++i) {
+    const Fr t1 = fr_mul(fr_mul(a[i], b[i]), c[i]);
+    const Fr t0 = fr_mul(fr_mul(fr_one_minus(a[i]), fr_one_minus(b[i])), fr_one_minus(c[i]));
+    acc = fr_mul(acc, fr_add(t1, t0));
+  }
+  return acc;
+}
+
+bool canonical_all(const void* p, uint64_t count) {
+  const Fr* f = static_cast<const Fr*>(p);
+  for (uint64_t i = 0; i < count; ++i)
+    if (!fr_is_canonical(f[i])) return false;
+  return true;
+}
+
+}  // namespace
+}  // namespace gkr
+
+using namespace gkr;
+
+extern "C" int32_t gkr_verify(const gkr_circuit* c, const gkr_fr* inputs, const gkr_fr* outputs,
+                              uint64_t seed, const uint8_t* proof, size_t proof_len) {
+  try {
+    if (!c || !inputs || !outputs || !proof) {
+      set_error("null argument");
+      return GKR_EINVAL;
+    }
+    const uint32_t d = c->depth, n = c->n;
+    size_t need = 0;
+    for (uint32_t i = 0; i < d; ++i) need += (6ull * c->s(i + 1) + 2) * 32;
+    if (proof_len != need) {
+      set_error("proof length " + std::to_string(proof_len) + ", expected " + std::to_string(need));
+      return GKR_EINVAL;
+    }
+    const uint64_t nin = 1ull << c->s(d), nout = 1ull << c->s(0);
+    if (!canonical_all(inputs, nin) || !canonical_all(outputs, nout) || !canonical_all(proof, need / 32)) {
+      set_error("element not canonical");
+      return GKR_EINVAL;
+    }
+    const Fr* pf = reinterpret_cast<const Fr*>(proof);
+    uint64_t pos = 0;
+
+    HostTranscript tr;
+    {
+      uint8_t msg[19];
+      memcpy(msg, "SISU-GKR-v1", 11);
+      for (int k = 0; k < 8; ++k) msg[11 + k] = (uint8_t)(seed >> (8 * k));
+      sha256_bytes(msg, sizeof(msg), tr.st.h);
+    }
+    uint32_t dig[8];
+    tr.absorb_words(kTagDigest, c->digest, 8);
+    tree_digest_host(reinterpret_cast<const uint8_t*>(inputs), nin * 32, dig);
+    tr.absorb_words(kTagDigest, dig, 8);
+    tree_digest_host(reinterpret_cast<const uint8_t*>(outputs), nout * 32, dig);
+    tr.absorb_words(kTagDigest, dig, 8);
+
+    std::vector<Fr> u(c->s(0)), v;
+    for (auto& x : u) x = to_m(tr.squeeze());
+    Fr vu = mle_host(outputs, c->s(0), u.data()), vv = fr_zero();
+    bool accept = true;
+    for (uint32_t i = 0; i < d; ++i) {
+      Fr alpha = fr_one(), beta = fr_zero();
+      if (i > 0) {
+        alpha = to_m(tr.squeeze());
+        beta = to_m(tr.squeeze());
+      }
+      Fr claim = fr_add(fr_mul(alpha, vu), fr_mul(beta, vv));
+      const uint32_t s1 = c->s(i + 1), sg = c->sigma[i], sg1 = c->sigma[i + 1];
+      std::vector<Fr> rxy[2];
+      Fr vals[2];
+      for (int phase = 0; phase < 2; ++phase) {
+        for (uint32_t j = 0; j < s1; ++j) {
+          const Fr* e = pf + pos;
+          pos += 3;
+          const Fr e0 = to_m(e[0]), e1 = to_m(e[1]), e2 = to_m(e[2]);
+          if (!fr_eq(fr_add(e0, e1), claim)) accept = false;
+          tr.absorb_elements(kTagRound, e, 3);
+          const Fr r = to_m(tr.squeeze());
+          rxy[phase].push_back(r);
+          claim = fr_interp3(e0, e1, e2, r);
+        }
+        vals[phase] = to_m(pf[pos]);
+        tr.absorb_elements(kTagValue, pf + pos, 1);
+        pos += 1;
+      }
+      const std::vector<Fr>& rx = rxy[0];
+      const std::vector<Fr>& ry = rxy[1];
+      // predicates
+      const std::vector<Fr> elx = eq_table_host(rx.data(), sg1), ely = eq_table_host(ry.data(), sg1);
+      const std::vector<Fr> wu = eq_table_host(u.data(), sg);
+      const Fr cu = triple_eq(u.data() + sg, rx.data() + sg1, ry.data() + sg1, n);
+      std::vector<Fr> wv;
+      Fr cv = fr_zero();
+      if (i > 0) {
+        wv = eq_table_host(v.data(), sg);
+        cv = triple_eq(v.data() + sg, rx.data() + sg1, ry.data() + sg1, n);
+      }
+      Fr add_v = fr_zero(), mul_v = fr_zero();
+      const std::vector<gkr_gate>& gl = c->gates[i];
+      for (size_t z = 0; z < gl.size(); ++z) {
+        Fr wgt = fr_mul(fr_mul(alpha, wu[z]), cu);
+        if (i > 0) wgt = fr_add(wgt, fr_mul(fr_mul(beta, wv[z]), cv));
+        const Fr term = fr_mul(fr_mul(wgt, elx[gl[z].x]), ely[gl[z].y]);
+        if (gl[z].type == GKR_GATE_MUL) mul_v = fr_add(mul_v, term);
+        else add_v = fr_add(add_v, term);
+      }
+      const Fr vx = vals[0], vy = vals[1];
+      const Fr fin = fr_add(fr_mul(fr_mul(mul_v, vx), vy), fr_mul(add_v, fr_add(vx, vy)));
+      if (!fr_eq(fin, claim)) accept = false;
+      u = rx;
+      v = ry;
+      vu = vx;
+      vv = vy;
+    }
+    if (accept) {
+      if (!fr_eq(vu, mle_host(inputs, c->s(d), u.data()))) accept = false;
+      if (accept && !fr_eq(vv, mle_host(inputs, c->s(d), v.data()))) accept = false;
+    }
+    return accept ? 1 : 0;
+  } catch (...) {
+    set_error("verifier failure (allocation)");
+    return GKR_ENOMEM;
+  }
+}

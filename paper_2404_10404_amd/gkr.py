@@ -1,0 +1,241 @@
+"""Python binding of the C ABI in include/gkr.h (argument marshalling only).
+
+Every step of proving runs in libgkr.so; this module converts arguments,
+allocates caller-owned device buffers through torch and checks status codes.
+If the library has not been built the import fails loudly: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgkr.so")
+
+GKR_OK = 0
+GKR_EINVAL = -1
+GKR_ENOMEM = -2
+GKR_EDEVICE = -3
+GKR_EBUFSZ = -4
+GKR_EUNSUPPORTED = -5
+
+# Every symbol include/gkr.h declares.
+EXPORTS = (
+    "gkr_last_error", "gkr_circuit_create", "gkr_circuit_destroy", "gkr_workspace_bytes",
+    "gkr_proof_bytes", "gkr_layer_proof_bytes", "gkr_gate_layers", "gkr_prove_circuit",
+    "gkr_transcript_init", "gkr_output_claim", "gkr_prove_layer", "gkr_verify",
+    "gkr_prove_batch", "gkr_batch_workspace_bytes", "gkr_set_tuning", "gkr_get_tuning",
+    "gkr_profile_enable", "gkr_profile_read",
+)
+
+
+class GkrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("gkr error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Gate(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_uint32), ("y", ctypes.c_uint32), ("type", ctypes.c_uint32)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+_i32 = ctypes.c_int32
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libgkr.so is not built; run __graft_entry__.build() "
+                              "or python -m paper_2404_10404_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        L.gkr_last_error.restype = ctypes.c_char_p
+        L.gkr_circuit_create.argtypes = [_u32, _u32, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.POINTER(Gate)),
+                                         ctypes.POINTER(_vp)]
+        L.gkr_circuit_create.restype = _i32
+        L.gkr_circuit_destroy.argtypes = [_vp]
+        L.gkr_circuit_destroy.restype = None
+        for name in ("gkr_workspace_bytes", "gkr_proof_bytes"):
+            getattr(L, name).argtypes = [_vp]
+            getattr(L, name).restype = _sz
+        L.gkr_layer_proof_bytes.argtypes = [_vp, _u32]
+        L.gkr_layer_proof_bytes.restype = _sz
+        L.gkr_gate_layers.argtypes = [_vp]
+        L.gkr_gate_layers.restype = _u64
+        L.gkr_prove_circuit.argtypes = [_vp, _vp, _u64, _vp, _vp, _sz, ctypes.POINTER(_sz), _vp, _sz, _vp]
+        L.gkr_prove_circuit.restype = _i32
+        L.gkr_transcript_init.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.gkr_transcript_init.restype = _i32
+        L.gkr_output_claim.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.gkr_output_claim.restype = _i32
+        L.gkr_prove_layer.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                      _sz, _vp]
+        L.gkr_prove_layer.restype = _i32
+        L.gkr_verify.argtypes = [_vp, _vp, _vp, _u64, _vp, _sz]
+        L.gkr_verify.restype = _i32
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise GkrError(rc, lib().gkr_last_error().decode())
+    return rc
+
+
+def _elements(arr) -> np.ndarray:
+    a = np.ascontiguousarray(arr, dtype=np.uint32)
+    if a.ndim != 2 or a.shape[1] != 8:
+        raise ValueError("elements must have shape (count, 8)")
+    return a
+
+
+class Circuit:
+    """A circuit object of the library (wiring uploaded to the current device)."""
+
+    def __init__(self, depth: int, log_copies: int, log_sub_width: Sequence[int],
+                 wiring: Sequence[Tuple[np.ndarray, np.ndarray, np.ndarray]]):
+        L = lib()
+        self.depth, self.log_copies = int(depth), int(log_copies)
+        self.log_sub_width = [int(s) for s in log_sub_width]
+        sig = (_u32 * len(self.log_sub_width))(*self.log_sub_width)
+        self._gate_arrays = []
+        ptrs = (ctypes.POINTER(Gate) * max(1, len(wiring)))()
+        for i, (x, y, t) in enumerate(wiring):
+            g = np.empty((len(x), 3), dtype=np.uint32)
+            g[:, 0], g[:, 1], g[:, 2] = x, y, t
+            self._gate_arrays.append(g)
+            ptrs[i] = g.ctypes.data_as(ctypes.POINTER(Gate))
+        h = _vp()
+        _check(L.gkr_circuit_create(self.depth, self.log_copies, sig, ptrs, ctypes.byref(h)))
+        self._h = h
+        self._gate_arrays = None
+
+    @classmethod
+    def from_synth(cls, spec, wiring) -> "Circuit":
+        return cls(spec.depth, spec.log_copies, spec.log_sub_width, [(w.x, w.y, w.kind) for w in wiring])
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().gkr_circuit_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def s(self, i: int) -> int:
+        return self.log_sub_width[i] + self.log_copies
+
+    @property
+    def workspace_bytes(self) -> int:
+        return lib().gkr_workspace_bytes(self._h)
+
+    @property
+    def proof_bytes(self) -> int:
+        return lib().gkr_proof_bytes(self._h)
+
+    def layer_proof_bytes(self, layer: int) -> int:
+        return lib().gkr_layer_proof_bytes(self._h, layer)
+
+    @property
+    def gate_layers(self) -> int:
+        return lib().gkr_gate_layers(self._h)
+
+
+# ------------------------------------------------------------ device-level calls
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def device_elements(arr, device="cuda"):
+    """Upload (count, 8) uint32 canonical elements as a torch int32 tensor."""
+    import torch
+    a = _elements(arr)
+    return torch.from_numpy(a.view(np.int32)).to(device)
+
+
+def host_elements(t) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint32).reshape(-1, 8)
+
+
+def alloc_bytes(nbytes: int, device="cuda"):
+    import torch
+    return torch.empty(max(1, (nbytes + 255) // 256 * 256), dtype=torch.uint8, device=device)
+
+
+def prove_circuit(c: Circuit, d_inputs, seed: int, d_outputs, d_proof, d_ws, stream=None) -> int:
+    """gkr_prove_circuit on caller tensors; returns the proof length."""
+    plen = _sz(0)
+    _check(lib().gkr_prove_circuit(c.handle, _ptr(d_inputs), seed & (2**64 - 1), _ptr(d_outputs), _ptr(d_proof),
+                                   d_proof.numel() * d_proof.element_size(), ctypes.byref(plen), _ptr(d_ws),
+                                   d_ws.numel() * d_ws.element_size(), _stream(stream)))
+    return plen.value
+
+
+def transcript_init(c: Circuit, seed: int, d_inputs, d_outputs, d_state, d_ws, stream=None):
+    _check(lib().gkr_transcript_init(c.handle, seed & (2**64 - 1), _ptr(d_inputs), _ptr(d_outputs), _ptr(d_state),
+                                     _ptr(d_ws), d_ws.numel() * d_ws.element_size(), _stream(stream)))
+
+
+def output_claim(c: Circuit, d_outputs, d_state, d_g, d_claim, d_ws, stream=None):
+    _check(lib().gkr_output_claim(c.handle, _ptr(d_outputs), _ptr(d_state), _ptr(d_g), _ptr(d_claim), _ptr(d_ws),
+                                  d_ws.numel() * d_ws.element_size(), _stream(stream)))
+
+
+def prove_layer(c: Circuit, layer: int, d_next, d_u, d_v, d_claim_u, d_claim_v, d_state, d_rx, d_ry, d_vx,
+                d_vy, d_layer_proof, d_ws, stream=None):
+    _check(lib().gkr_prove_layer(c.handle, layer, _ptr(d_next), _ptr(d_u), _ptr(d_v), _ptr(d_claim_u),
+                                 _ptr(d_claim_v), _ptr(d_state), _ptr(d_rx), _ptr(d_ry), _ptr(d_vx), _ptr(d_vy),
+                                 _ptr(d_layer_proof), _ptr(d_ws), d_ws.numel() * d_ws.element_size(),
+                                 _stream(stream)))
+
+
+def verify(c: Circuit, inputs, outputs, seed: int, proof: bytes) -> int:
+    """gkr_verify on host buffers: 1 accept, 0 reject (raises on malformed input)."""
+    a, b = _elements(inputs), _elements(outputs)
+    pb = np.frombuffer(bytes(proof), dtype=np.uint8)
+    return _check(lib().gkr_verify(c.handle, a.ctypes.data, b.ctypes.data, seed & (2**64 - 1),
+                                   pb.ctypes.data if pb.size else None, pb.size))
+
+
+class Prover:
+    """Owns the device buffers of one plain proof at a time for one circuit."""
+
+    def __init__(self, c: Circuit, device="cuda"):
+        import torch
+        self.c = c
+        self.device = device
+        self.ws = alloc_bytes(c.workspace_bytes, device)
+        self.proof = alloc_bytes(c.proof_bytes, device)
+        self.outputs = torch.empty((1 << c.s(0), 8), dtype=torch.int32, device=device)
+
+    def prove(self, d_inputs, seed: int, stream=None) -> int:
+        return prove_circuit(self.c, d_inputs, seed, self.outputs, self.proof, self.ws, stream)
+
+    def proof_bytes(self) -> bytes:
+        return bytes(self.proof[: self.c.proof_bytes].cpu().numpy().tobytes())

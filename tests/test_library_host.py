@@ -1,0 +1,106 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library loads, exports every symbol include/gkr.h declares, validates
+circuits, and its host verifier (gkr_verify) agrees with the oracle: it
+accepts oracle proofs and rejects tampered ones. The verifier shares the
+library's field arithmetic and SHA-256 with the device code, so this also
+pins those routines against the oracle on the CPU.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gkr_synth as gs
+from oracle import circuit as oc
+from oracle import prover as op
+from oracle.field import P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+gkr = pytest.importorskip("paper_2404_10404_amd.gkr")
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "gkr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gkr_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = gkr.lib()
+    syms = _declared_symbols()
+    assert "gkr_prove_circuit" in syms and "gkr_verify" in syms and "gkr_prove_layer" in syms
+    missing = [s for s in syms if not hasattr(L, s)]
+    assert not missing, missing
+
+
+def _case(depth, n, sig, seed, mu=(1, 2)):
+    spec = gs.CircuitSpec(depth=depth, log_copies=n, log_sub_width=tuple(sig), mu=mu, seed=seed)
+    wiring = gs.make_wiring(spec)
+    inputs = gs.make_inputs(spec)
+    oc_ = oc.Circuit.from_synth(spec, wiring)
+    pt = op.prove(oc_, gs.elements_to_ints(inputs), seed)
+    return spec, wiring, inputs, pt
+
+
+@pytest.mark.parametrize("shape", [
+    (4, 0, (10,) * 5, 1),
+    (3, 3, (4, 5, 3, 4), 7),
+    (2, 5, (0, 2, 1), 8),
+    (1, 0, (0, 0), 9),
+    (3, 2, (2, 0, 3, 1), 10),
+    (2, 4, (6, 6, 6), 11),
+])
+def test_host_verifier_accepts_oracle_proofs(shape):
+    depth, n, sig, seed = shape
+    spec, wiring, inputs, pt = _case(depth, n, sig, seed)
+    c = gkr.Circuit.from_synth(spec, wiring)
+    assert c.proof_bytes == op.proof_length(oc.Circuit.from_synth(spec, wiring))
+    assert c.gate_layers == spec.gate_layers
+    outs = gs.ints_to_elements(pt.outputs)
+    proof = pt.proof_bytes()
+    assert gkr.verify(c, inputs, outs, seed, proof) == 1
+    # any changed element of the proof is rejected
+    for k in range(0, len(proof) // 32, max(1, len(proof) // 32 // 17)):
+        bad = bytearray(proof)
+        v = int.from_bytes(bad[32 * k:32 * k + 32], "little")
+        bad[32 * k:32 * k + 32] = ((v + 1) % P).to_bytes(32, "little")
+        assert gkr.verify(c, inputs, outs, seed, bytes(bad)) == 0
+    # wrong seed (a proof with no round draws no challenge, so only then)
+    if any(spec.log_width(i) for i in range(depth + 1)):
+        assert gkr.verify(c, inputs, outs, seed + 1, proof) == 0
+    outs2 = outs.copy()
+    outs2[0, 0] ^= 1
+    if gs.elements_to_ints(outs2[:1])[0] < P:
+        assert gkr.verify(c, inputs, outs2, seed, proof) == 0
+
+
+def test_host_verifier_rejects_malformed():
+    spec, wiring, inputs, pt = _case(2, 1, (2, 2, 2), 3)
+    c = gkr.Circuit.from_synth(spec, wiring)
+    outs = gs.ints_to_elements(pt.outputs)
+    proof = pt.proof_bytes()
+    with pytest.raises(gkr.GkrError) as e:
+        gkr.verify(c, inputs, outs, 3, proof[:-32])
+    assert e.value.code == gkr.GKR_EINVAL
+    bad = bytearray(proof)
+    bad[0:32] = P.to_bytes(32, "little")
+    with pytest.raises(gkr.GkrError):
+        gkr.verify(c, inputs, outs, 3, bytes(bad))
+
+
+def test_circuit_validation():
+    x = np.zeros(4, np.uint32)
+    with pytest.raises(gkr.GkrError) as e:
+        gkr.Circuit(1, 0, [2, 1], [(x + 2, x, x)])  # x index beyond the next layer
+    assert e.value.code == gkr.GKR_EINVAL
+    with pytest.raises(gkr.GkrError):
+        gkr.Circuit(1, 0, [2, 2], [(x, x, x + 2)])  # unknown gate type
+    with pytest.raises(gkr.GkrError) as e:
+        gkr.Circuit(1, 30, [2, 2], [(x, x, x)])
+    assert e.value.code == gkr.GKR_EUNSUPPORTED
+    with pytest.raises(gkr.GkrError):
+        gkr.Circuit(0, 0, [2], [])

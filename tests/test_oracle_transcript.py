@@ -32,13 +32,13 @@ def test_transcript_chain_by_hand():
     tr = T.Transcript(5)
     st0 = hashlib.sha256(b"SISU-GKR-v1" + struct.pack("<Q", 5)).digest()
     assert tr.state == st0
-    tr.absorb(b"D", b"xyz")
-    st1 = hashlib.sha256(st0 + b"D" + b"xyz").digest()
+    tr.absorb(b"GKRD", b"xyz")
+    st1 = hashlib.sha256(st0 + b"GKRD" + b"xyz").digest()
     assert tr.state == st1
     v = tr.squeeze()
     st = st1
     while True:
-        st = hashlib.sha256(st + b"C").digest()
+        st = hashlib.sha256(st + b"GKRC").digest()
         cand = int.from_bytes(st, "little") % (1 << 254)
         if cand < F.P:
             break
@@ -64,7 +64,7 @@ def test_rejection_happens_at_the_expected_rate():
         v = tr.squeeze()
         s, k = st, 0
         while True:
-            s = hashlib.sha256(s + b"C").digest()
+            s = hashlib.sha256(s + b"GKRC").digest()
             k += 1
             if int.from_bytes(s, "little") % (1 << 254) < F.P:
                 break
