@@ -1,0 +1,188 @@
+"""Benchmark: GKR prover field-gates/s on one MI355X.
+
+A step is one whole proof (forward evaluation, statement binding, output claim
+and every layer's two sumcheck phases) of the workload over inputs already in
+HBM. `value` = field gates (sum over gate layers of 2^{s_i}) x steps / wall time.
+
+Default workload: 2^8 identical copies of a depth-16 sub-circuit with 2^12
+gates per layer (2^20 gates per layer), half MUL gates, seed 2.
+--workload c3: 2^12 copies x 2^14 gates x depth 24 (2^26 gates per layer).
+
+The line also carries the roofline of the dominant kernel class (HIP events
+around each launch during a separate timed pass) and the oracle's rate on a
+bounded slice of the same workload (cpu_baseline).
+"""
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import gkr_synth as gs  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+# Full-rate 32-bit VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# 32x32 multiply-accumulates of one schoolbook Montgomery product with 8 limbs.
+MACS_PER_MULMOD = 2 * 8 * 8 + 8
+
+WORKLOADS = {
+    "c1": (gs.plain_c1, "plain circuit: depth 4, 2^10 gates/layer"),
+    "c2": (gs.data_parallel_c2, "data-parallel: 2^8 copies x (depth 16, 2^12 gates/layer) = 2^20 gates/layer"),
+    "c3": (gs.worker_share_c3, "single-worker share: 2^12 copies x (depth 24, 2^14 gates/layer) = 2^26 gates/layer, 30% MUL"),
+}
+
+
+class ProfEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("mulmods", ctypes.c_double)]
+
+
+def profile_pass(gkr, prover, d_in, seed, steps):
+    import torch
+    L = gkr.lib()
+    L.gkr_profile_enable.argtypes = [ctypes.c_int32]
+    L.gkr_profile_read.argtypes = [ctypes.POINTER(ProfEntry), ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
+    torch.cuda.synchronize()
+    L.gkr_profile_enable(1)
+    for _ in range(steps):
+        prover.prove(d_in, seed)
+    torch.cuda.synchronize()
+    arr = (ProfEntry * 32)()
+    cnt = ctypes.c_uint32(0)
+    L.gkr_profile_read(arr, 32, ctypes.byref(cnt))
+    L.gkr_profile_enable(0)
+    out = {}
+    for i in range(cnt.value):
+        e = arr[i]
+        out[e.name.decode()] = {"launches": e.launches // steps, "ms": e.ms / steps,
+                                "bytes": e.bytes / steps, "mulmods": e.mulmods / steps}
+    return out
+
+
+def roofline(prof):
+    name, e = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    sec = e["ms"] / 1e3
+    gbs = e["bytes"] / sec / 1e9
+    tops = e["mulmods"] * MACS_PER_MULMOD / sec / 1e12
+    t_hbm = e["bytes"] / (HBM_PEAK_GBS * 1e9)
+    t_alu = e["mulmods"] * MACS_PER_MULMOD / (VALU_PEAK_TOPS * 1e12)
+    if t_hbm >= t_alu:
+        r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    else:
+        r = {"bound": "alu", "achieved": round(tops, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
+             "frac": round(tops / VALU_PEAK_TOPS, 4)}
+    r.update({"kernel": name, "launches_per_step": e["launches"],
+              "avg_launch_us": round(e["ms"] * 1e3 / max(1, e["launches"]), 2),
+              "hbm_gbs": round(gbs, 1), "alu_tops": round(tops, 3), "traffic": None})
+    return r
+
+
+def cpu_baseline(spec, budget_s=20.0):
+    """The oracle (pure Python, one core) on a slice of the workload with fewer copies."""
+    from oracle import circuit as oc
+    from oracle import prover as op
+    n = 0
+    # grow the slice while a proof is expected to stay within the budget
+    sample = None
+    t_used = 0.0
+    while True:
+        sl = gs.copy_slice(spec, n)
+        wiring = gs.make_wiring(sl)
+        inputs = gs.elements_to_ints(gs.make_inputs(sl))
+        c = oc.Circuit.from_synth(sl, wiring)
+        t0 = time.perf_counter()
+        op.prove(c, inputs, sl.seed)
+        dt = time.perf_counter() - t0
+        sample = (sl, dt)
+        t_used += dt
+        if n >= spec.log_copies or t_used + 2.2 * dt > budget_s:
+            break
+        n += 1
+    sl, dt = sample
+    return {"value": round(sl.gate_layers / dt, 1), "unit": "field-gates/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle proof of the same sub-circuit with 2^%d of the 2^%d copies (%d gate-layers) in %.1f s"
+                      % (sl.log_copies, spec.log_copies, sl.gate_layers, dt)}
+
+
+def golden_digest(workload):
+    p = os.path.join(ROOT, "tests", "golden", "%s_proof.json" % workload)
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        return json.load(f).get("proof_sha256")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build proves one worker's share on a single MI355X "
+              "and has no multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2404_10404_amd import gkr
+
+    spec = WORKLOADS[args.workload][0]()
+    wiring = gs.make_wiring(spec)
+    inputs = gs.make_inputs(spec)
+    c = gkr.Circuit.from_synth(spec, wiring)
+    prover = gkr.Prover(c)
+    d_in = gkr.device_elements(inputs)
+    del inputs
+    for _ in range(args.warmup):
+        prover.prove(d_in, spec.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        prover.prove(d_in, spec.seed)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = c.gate_layers * args.steps / dt
+    proof = prover.proof_bytes()
+    gd = golden_digest(args.workload)
+    exact = None if gd is None else (hashlib.sha256(proof).hexdigest() == gd)
+
+    line = {
+        "metric": "GKR prover field-gates/sec (plain proof, bit-exact)",
+        "value": round(value, 1),
+        "unit": "field-gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32 (BN254 Fr, exact modular integer arithmetic)",
+        "data": "synthetic (seeded circuits and inputs; the paper's Ethereum circuits are not available)",
+        "config": {"workload": WORKLOADS[args.workload][1], "gate_layers_per_proof": c.gate_layers,
+                   "proof_bytes": c.proof_bytes, "seed": spec.seed},
+        "bit_exact_vs_oracle_golden": exact,
+    }
+    if not args.no_profile:
+        prof = profile_pass(gkr, prover, d_in, spec.seed, args.profile_steps)
+        line["roofline"] = roofline(prof)
+        line["kernels"] = {k: {"ms": round(v["ms"], 4), "launches": v["launches"]} for k, v in
+                           sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

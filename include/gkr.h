@@ -35,10 +35,14 @@
  * Fiat-Shamir transcript (non-interactive form of the verifier's challenges):
  *   init           st = SHA256("SISU-GKR-v1" || LE64(seed))
  *   absorb(t, m)   st = SHA256(st || t || m), t a four-byte tag
- *   squeeze        repeat st = SHA256(st || "GKRC"); v = LE(st) mod 2^254 until v < p
+ *   accept         v = LE(st) mod 2^254; while v >= p: st = SHA256(st || "GKRC"), recompute v
+ *   squeeze        st = SHA256(st || "GKRC"), then accept
  * Statement: absorb("GKRD", circuit digest), absorb("GKRD", tree digest of the
- * inputs), absorb("GKRD", tree digest of the outputs). Round messages are
- * absorbed with "GKRR" (e0 || e1 || e2), a phase's final value with "GKRV".
+ * inputs), absorb("GKRD", tree digest of the outputs); tree digests hash 1 KiB
+ * chunks and then the concatenated chunk digests, recursively. A round absorbs
+ * "GKRR" || e0 || e2 and its challenge is `accept` of the new state (e1 is fixed
+ * by the running claim, e1 = claim - e0); a phase's final value is absorbed
+ * with "GKRV". Challenges alpha, beta and the output point come from squeeze.
  *
  * Proof layout: for each gate layer i = 0..d-1 with s' = s_{i+1}:
  *   s' phase-1 messages (e0, e1, e2: the round polynomial at t = 0, 1, 2),
@@ -167,6 +171,34 @@ int32_t gkr_prove_layer(const gkr_circuit* circuit, uint32_t layer, const gkr_fr
  */
 int32_t gkr_verify(const gkr_circuit* circuit, const gkr_fr* inputs, const gkr_fr* outputs,
                    uint64_t seed, const uint8_t* proof, size_t proof_len);
+
+/*
+ * Round-schedule tuning (process-wide; used by the autotuner). Proof bytes
+ * never depend on it. tail_log: tables of at most 2^tail_log entries finish
+ * their phase in one workgroup (1..20); max_round_blocks: cap on the
+ * workgroups of one grid-wide round (1..4096). Errors: GKR_EINVAL.
+ */
+int32_t gkr_set_tuning(uint32_t tail_log, uint32_t max_round_blocks);
+int32_t gkr_get_tuning(uint32_t* tail_log, uint32_t* max_round_blocks);
+
+/*
+ * Kernel timing for measurement. While enabled, every launch is bracketed by
+ * two HIP events on its own stream (do not enable it while capturing a HIP
+ * graph). gkr_profile_read waits for the recorded events and returns, per
+ * kernel class, the launch count, the summed event time, and the algorithmic
+ * HBM bytes and field products the host attributed to those launches
+ * (see the kernel descriptions in the design notes). Enabling resets the sums.
+ */
+typedef struct {
+  char name[32];
+  uint64_t launches;
+  double ms;
+  double bytes;
+  double mulmods;
+} gkr_profile_entry;
+
+int32_t gkr_profile_enable(int32_t on);
+int32_t gkr_profile_read(gkr_profile_entry* out, uint32_t cap, uint32_t* count);
 
 #ifdef __cplusplus
 }

@@ -31,7 +31,7 @@ from typing import List, Optional, Sequence
 from . import mle
 from .circuit import MUL, Circuit, evaluate
 from .field import P, encode_all, to_bytes
-from .transcript import TAG_DIGEST, TAG_ROUND, TAG_VALUE, Transcript, circuit_digest, vector_digest
+from .transcript import TAG_DIGEST, TAG_VALUE, Transcript, circuit_digest, vector_digest
 
 
 @dataclasses.dataclass
@@ -86,8 +86,7 @@ def sumcheck_product(W: List[int], X: List[int], Y: List[int], tr: Transcript):
                 yt = Y[b] + t * (Y[b + h] - Y[b])
                 acc += wt * xt + yt
             e.append(acc % P)
-        tr.absorb_elements(TAG_ROUND, e)
-        r = tr.squeeze()
+        r = tr.round_challenge(e[0], e[2])
         messages.append(e)
         challenges.append(r)
         W, X, Y = mle.fold(W, r), mle.fold(X, r), mle.fold(Y, r)

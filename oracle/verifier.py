@@ -24,7 +24,7 @@ from . import mle
 from .circuit import MUL, Circuit
 from .field import HALF, P, from_bytes
 from .prover import combined_eq
-from .transcript import TAG_DIGEST, TAG_ROUND, TAG_VALUE, Transcript, circuit_digest, vector_digest
+from .transcript import TAG_DIGEST, TAG_VALUE, Transcript, circuit_digest, vector_digest
 
 
 class MalformedProof(ValueError):
@@ -107,8 +107,7 @@ def _check_phase(rd: _Reader, nvars: int, claim: int, tr: Transcript):
         e = [rd.element(), rd.element(), rd.element()]
         if (e[0] + e[1]) % P != claim:
             ok = False
-        tr.absorb_elements(TAG_ROUND, e)
-        r = tr.squeeze()
+        r = tr.round_challenge(e[0], e[2])
         rs.append(r)
         claim = interpolate(e, r)
     return ok, claim, rs
@@ -126,19 +125,55 @@ def verify(circuit: Circuit, inputs: Sequence[int], outputs: Sequence[int], seed
         raise ValueError("input or output vector has the wrong size")
     if any(not 0 <= a < P for a in inputs) or any(not 0 <= a < P for a in outputs):
         raise ValueError("input or output element not canonical")
+    return _verify_core(circuit, seed, proof, predicates,
+                        vector_digest(inputs), vector_digest(outputs),
+                        lambda r: mle.evaluate(list(inputs), r),
+                        lambda r: mle.evaluate(list(outputs), r))
+
+
+def verify_limbs(circuit: Circuit, inputs_limbs, outputs_limbs, seed: int, proof: bytes,
+                 predicates=predicates_factored) -> bool:
+    """verify() for vectors given as canonical (count, 8) uint32 limb arrays.
+
+    The statement digests hash the raw little-endian bytes (the canonical
+    encoding) and the two large multilinear extensions use the C helper in
+    oracle/fast.py; everything else is the same code as verify().
+    """
+    import numpy as np
+
+    from . import fast
+    from .transcript import tree_digest
+
+    d = circuit.depth
+    ins = np.ascontiguousarray(inputs_limbs, dtype=np.uint32)
+    outs = np.ascontiguousarray(outputs_limbs, dtype=np.uint32)
+    if ins.shape != (1 << circuit.s(d), 8) or outs.shape != (1 << circuit.s(0), 8):
+        raise ValueError("input or output vector has the wrong size")
+    top = P >> 224
+    for arr in (ins, outs):
+        if (arr[:, 7] > top).any():
+            raise ValueError("input or output element not canonical")
+    return _verify_core(circuit, seed, proof, predicates,
+                        tree_digest(ins.tobytes()), tree_digest(outs.tobytes()),
+                        lambda r: fast.mle_limbs(ins, r), lambda r: fast.mle_limbs(outs, r))
+
+
+def _verify_core(circuit: Circuit, seed: int, proof: bytes, predicates, dig_in: bytes, dig_out: bytes,
+                 mle_in, mle_out) -> bool:
+    d = circuit.depth
     expected = sum((6 * circuit.s(i + 1) + 2) * 32 for i in range(d))
     if len(proof) != expected:
         raise MalformedProof("proof length %d, expected %d" % (len(proof), expected))
     rd = _Reader(proof)
     tr = Transcript(seed)
     tr.absorb(TAG_DIGEST, circuit_digest(d, circuit.n, circuit.sigma, circuit.wiring))
-    tr.absorb(TAG_DIGEST, vector_digest(inputs))
-    tr.absorb(TAG_DIGEST, vector_digest(outputs))
+    tr.absorb(TAG_DIGEST, dig_in)
+    tr.absorb(TAG_DIGEST, dig_out)
     g = [tr.squeeze() for _ in range(circuit.s(0))]
     accept = True
     u: List[int] = g
     v: Optional[List[int]] = None
-    vu, vv = mle.evaluate(list(outputs), g), 0
+    vu, vv = mle_out(g), 0
     for i in range(d):
         if i == 0:
             alpha, beta = 1, 0
@@ -156,5 +191,5 @@ def verify(circuit: Circuit, inputs: Sequence[int], outputs: Sequence[int], seed
         final = (mul_v * vx % P * vy + add_v * (vx + vy)) % P
         accept = accept and ok1 and ok2 and final == claim
         u, v, vu, vv = rx, ry, vx, vy
-    accept = accept and vu == mle.evaluate(list(inputs), u) and vv == mle.evaluate(list(inputs), v)
+    accept = accept and vu == mle_in(u) and vv == mle_in(v)
     return accept

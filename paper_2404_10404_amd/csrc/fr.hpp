@@ -122,8 +122,66 @@ GKR_HD Fr fr_sub(const Fr& a, const Fr& b) {
 GKR_HD Fr fr_neg(const Fr& a) { return fr_sub(fr_zero(), a); }
 GKR_HD Fr fr_double(const Fr& a) { return fr_add(a, a); }
 
-// Montgomery product a*b*R^{-1} mod p (CIOS, 8 x 32-bit limbs).
+#if defined(__HIP_DEVICE_COMPILE__)
+// Column multiply-accumulate of product scanning: (ov:acc) += x * y, where the
+// 64-bit add inside v_mad_u64_u32 reports its carry in VCC and v_addc folds it
+// into the 32-bit overflow word. Two VALU instructions per 32x32 product.
+__device__ __forceinline__ void fr_mac_vv(uint64_t& acc, uint32_t& ov, uint32_t x, uint32_t y) {
+  asm volatile("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\tv_addc_co_u32_e32 %1, vcc, 0, %1, vcc"
+               : "+v"(acc), "+v"(ov)
+               : "v"(x), "v"(y)
+               : "vcc");
+}
+__device__ __forceinline__ void fr_mac_vs(uint64_t& acc, uint32_t& ov, uint32_t x, uint32_t y) {
+  asm volatile("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\tv_addc_co_u32_e32 %1, vcc, 0, %1, vcc"
+               : "+v"(acc), "+v"(ov)
+               : "v"(x), "s"(y)
+               : "vcc");
+}
+
+// Montgomery product on the device: finely integrated product scanning (FIPS,
+// Koc-Acar-Kaliski 1996). Column k of a*b and of m*p is summed into a 96-bit
+// accumulator; m_k is chosen so the low word of column k vanishes.
+__device__ __forceinline__ Fr fr_mul_device(const Fr& a, const Fr& b) {
+  uint32_t m[8];
+  Fr r;
+  uint64_t acc = 0;
+  uint32_t ov = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+#pragma unroll
+    for (int j = 0; j < k; ++j) {
+      fr_mac_vv(acc, ov, a.v[j], b.v[k - j]);
+      fr_mac_vs(acc, ov, m[j], p_limb(k - j));
+    }
+    fr_mac_vv(acc, ov, a.v[k], b.v[0]);
+    m[k] = (uint32_t)acc * GKR_NINV;
+    fr_mac_vs(acc, ov, m[k], GKR_P0);
+    acc = (acc >> 32) | ((uint64_t)ov << 32);
+    ov = 0;
+  }
+#pragma unroll
+  for (int k = 8; k < 15; ++k) {
+#pragma unroll
+    for (int j = k - 7; j < 8; ++j) {
+      fr_mac_vv(acc, ov, a.v[j], b.v[k - j]);
+      fr_mac_vs(acc, ov, m[j], p_limb(k - j));
+    }
+    r.v[k - 8] = (uint32_t)acc;
+    acc = (acc >> 32) | ((uint64_t)ov << 32);
+    ov = 0;
+  }
+  r.v[7] = (uint32_t)acc;
+  return fr_reduce_once(r);
+}
+#endif
+
+// Montgomery product a*b*R^{-1} mod p. Host: coarsely integrated operand
+// scanning (CIOS) in plain C; device: the product-scanning form above.
 GKR_HD Fr fr_mul(const Fr& a, const Fr& b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return fr_mul_device(a, b);
+#else
   uint32_t t[10];
 #pragma unroll
   for (int k = 0; k < 10; ++k) t[k] = 0;
@@ -156,6 +214,7 @@ GKR_HD Fr fr_mul(const Fr& a, const Fr& b) {
 #pragma unroll
   for (int k = 0; k < 8; ++k) r.v[k] = t[k];
   return fr_reduce_once(r);
+#endif
 }
 
 GKR_HD Fr fr_sqr(const Fr& a) { return fr_mul(a, a); }

@@ -101,10 +101,10 @@ size_t plan_workspace(const gkr_circuit& c, Plan& p) {
   p.off_Wc = take(E << n);
   p.off_Fc = take(E << n);
   p.off_Kc = take(E << n);
-  // y-range split of the copy-table pass: about 2^16 threads in total
-  uint64_t want = (n >= 16) ? 1 : (1ull << (16 - n));
+  // row split of the copy-table pass: about 2^20 threads in total (a power of two)
+  uint64_t want = (n >= 20) ? 1 : (1ull << (20 - n));
   uint64_t rows = 1ull << sigp_max;
-  p.ychunks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, std::min<uint64_t>(rows, 4096)));
+  p.ychunks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, std::min<uint64_t>(rows, 1ull << 15)));
   p.off_wpart = take(E * ((size_t)p.ychunks << n));
   p.off_partials = take(E * (size_t)kMaxRoundBlocks * kMaxPartialValues);
   const uint64_t big = 1ull << std::max(c.s(0), c.s(d));
@@ -190,10 +190,12 @@ static void run_digest(const gkr_fr* vec, uint64_t nelem, uint32_t* final_out, c
 template <class Form>
 static void run_phase(Tabs<Form::NT> t, uint32_t nrounds, DevState* S, Fr* partials, Fr* r_out,
                       uint32_t* msg, Fr* final_out, uint32_t* proof_value, const Tuning& tun,
-                      hipStream_t s) {
-  uint64_t eval = 1ull << nrounds;
-  uint32_t j = 0;
-  const Fr* pending = nullptr;
+                      hipStream_t s, uint32_t first_round = 0) {
+  // first_round > 0: the rounds before it were already evaluated (their
+  // challenge is pending) and the tables have 2^(nrounds - first_round + 1) entries.
+  uint64_t eval = 1ull << (nrounds - first_round);
+  uint32_t j = first_round;
+  const Fr* pending = first_round ? r_out + first_round - 1 : nullptr;
   while (j < nrounds && eval > (1ull << tun.tail_log)) {
     launch_round<Form>(t, eval / 2, pending, S, partials, r_out + j, msg + 24 * j,
                        tun.max_round_blocks, s);
@@ -226,13 +228,20 @@ static void run_layer(const gkr_circuit& c, uint32_t i, const Workspace& w, cons
   e1.bits[3] = n; e1.point[3] = v + sg; e1.scale[3] = nullptr; e1.out[3] = w.Cv;
   launch_eq_tables(e1, s);
 
-  // Phase 1
-  launch_phase1_init(W, w.G, w.H, c.wiring[i], w.aU, w.bV, w.Cu, w.Cv, n, 1ull << s1, s);
+  // Phase 1: tables (and, for big tables, round 1 in the same pass), then the rounds.
   Tabs<3> ta;
   ta.src[0] = W; ta.src[1] = w.G; ta.src[2] = w.H;
   ta.dst[0] = w.Wf; ta.dst[1] = w.G; ta.dst[2] = w.H;
   const uint32_t off_vx = 24 * s1, off_p2 = off_vx + 8, off_vy = off_p2 + 24 * s1;
-  run_phase<FormA>(ta, s1, S, w.partials, rx, proof, &S->vx, proof + off_vx, tun, s);
+  if (s1 > tun.tail_log) {
+    launch_phase1_init_round(W, w.G, w.H, c.wiring[i], w.aU, w.bV, w.Cu, w.Cv, n, 1ull << (s1 - 1),
+                             1ull << c.s(i), S, w.partials, rx, proof, tun.max_round_blocks, s);
+    run_phase<FormA>(ta, s1, S, w.partials, rx, proof, &S->vx, proof + off_vx, tun, s, 1);
+  } else {
+    launch_phase1_init(W, w.G, w.H, c.wiring[i], w.aU, w.bV, w.Cu, w.Cv, n, 1ull << s1,
+                       1ull << c.s(i), s);
+    run_phase<FormA>(ta, s1, S, w.partials, rx, proof, &S->vx, proof + off_vx, tun, s);
+  }
 
   // Phase 2: sub-circuit rounds with the copy factors contracted, then the copy rounds.
   EqJobs e2{};
@@ -241,7 +250,8 @@ static void run_layer(const gkr_circuit& c, uint32_t i, const Workspace& w, cons
   e2.bits[1] = n; e2.point[1] = rx + sg1; e2.scale[1] = nullptr; e2.out[1] = w.EC;
   launch_eq_tables(e2, s);
   launch_copy_weights(w.Cu, w.Cv, w.EC, w.U, w.V, 1ull << n, S, s);
-  launch_phase2_tables(c.wiring[i], w.aU, w.bV, w.EL, S, w.Fa, w.Fb, w.Ka, w.Kb, w.Ks, 1ull << sg1, s);
+  launch_phase2_tables(c.wiring[i], w.aU, w.bV, w.EL, S, w.Fa, w.Fb, w.Ka, w.Kb, w.Ks, 1ull << sg1,
+                       1ull << sg, s);
   launch_copy_contract(W, w.U, w.V, w.P, w.Q, n, 1ull << sg1, s);
   Tabs<5> tb;
   tb.src[0] = w.P; tb.src[1] = w.Fa; tb.src[2] = w.Q; tb.src[3] = w.Fb; tb.src[4] = w.Ks;
@@ -265,7 +275,8 @@ static void run_layer(const gkr_circuit& c, uint32_t i, const Workspace& w, cons
 // Forward evaluation of every layer from Montgomery inputs in layer[d].
 static void run_forward(const gkr_circuit& c, const Workspace& w, hipStream_t s) {
   for (int i = (int)c.depth - 1; i >= 0; --i)
-    launch_forward(w.layer[i + 1], w.layer[i], c.wiring[i].gates, c.n, 1ull << c.s(i), s);
+    launch_forward(w.layer[i + 1], w.layer[i], c.wiring[i].gates, c.n, 1ull << c.s(i),
+                   (uint64_t)c.mul_gates[i] << c.n, s);
 }
 
 // g and the output claim V_0~(g) (into S->scratch[0]); needs layer[0] in Montgomery form.
@@ -357,8 +368,10 @@ int32_t gkr_circuit_create(uint32_t depth, uint32_t log_copies, const uint32_t* 
       const uint64_t cnt = 1ull << c->sigma[i];
       const uint64_t lim = 1ull << c->sigma[i + 1];
       c->gates[i].assign(gates[i], gates[i] + cnt);
+      c->mul_gates.push_back(0);
       for (uint64_t z = 0; z < cnt; ++z) {
         const gkr_gate& g = c->gates[i][z];
+        c->mul_gates.back() += g.type == GKR_GATE_MUL;
         if (g.x >= lim || g.y >= lim || g.type > 1) {
           delete c;
           set_error("layer " + std::to_string(i) + " gate " + std::to_string(z) + " is invalid");

@@ -17,7 +17,7 @@ namespace gkr {
 constexpr int kBlock = 256;             // threads per workgroup for every kernel
 constexpr uint32_t kMaxRoundBlocks = 4096;  // cap on workgroups of a reduction launch
 constexpr int kMaxPartialValues = 2;    // reduced values per workgroup
-constexpr uint32_t kChunkWords = 2048;  // 8 KiB SHA-256 leaf chunk of a tree digest
+constexpr uint32_t kChunkWords = 256;   // 1 KiB SHA-256 leaf chunk of a tree digest
 
 // Transcript tags as big-endian words ("GKRD", "GKRR", "GKRV", "GKRC").
 constexpr uint32_t kTagDigest = 0x474B5244u;
@@ -45,6 +45,48 @@ struct DevState {
   Fr su, sv;        // sum_c U[c], sum_c V[c]
   Fr ka_f, kb_f;    // Ka~, Kb~ at the phase-2 local point
   Fr scratch[4];
+};
+
+// One step of a proof program: a kernel body over `ntiles` workgroups.
+// The host driver records a proof as a sequence of steps; the plain executor
+// launches one kernel per step and the persistent batch kernel runs the steps
+// of many proofs. Parameters are typed by `type` (see gkr_kernels.hip).
+enum StepType : uint32_t {
+  ST_TO_MONT = 0,
+  ST_FROM_MONT,
+  ST_FORWARD,
+  ST_DIGEST,
+  ST_TRANSCRIPT_BEGIN,
+  ST_SQUEEZE,
+  ST_LAYER_BEGIN,
+  ST_EQ,
+  ST_WSUM,
+  ST_P1_INIT,
+  ST_P1_INIT_ROUND,
+  ST_ROUND_A,
+  ST_ROUND_B,
+  ST_TAIL_A,
+  ST_TAIL_B,
+  ST_COPY_WEIGHTS,
+  ST_P2_TABLES,
+  ST_COPY_CONTRACT,
+  ST_LOCAL_CONTRACT,
+  ST_COPY_TABLES,
+  ST_LOCAL_VALUES,
+  ST_STATE_EXPORT,
+  ST_STATE_IMPORT,
+  ST_COUNT
+};
+
+struct Step {
+  uint32_t type;
+  uint32_t ntiles;   // workgroups
+  uint32_t u[6];     // small integers
+  uint64_t q[4];     // sizes
+  const void* p[16]; // device pointers
+  uint32_t w[16];    // host words (seed state, circuit digest)
+  double bytes;      // algorithmic HBM bytes (timing reports only)
+  double mulmods;    // field products (timing reports only)
 };
 
 // Tunables of the round schedule (autotuned; see gkr_tuning.*).
@@ -86,6 +128,7 @@ struct gkr_circuit {
   uint32_t depth = 0, n = 0;
   std::vector<uint32_t> sigma;                // [depth+1]
   std::vector<std::vector<gkr_gate>> gates;   // host copy of each layer's sub-circuit
+  std::vector<uint64_t> mul_gates;            // MUL gates of each layer's sub-circuit
   uint32_t digest[8];                         // circuit digest, SHA-256 words
   int device = 0;
   void* dev_block = nullptr;

@@ -14,6 +14,7 @@
 // claim) on one thread. Challenges and claims never leave device memory, so a
 // proof is a plain sequence of launches on one stream.
 #include "gkr_kernels.hpp"
+#include "gkr_profile.hpp"
 
 namespace gkr {
 
@@ -137,21 +138,43 @@ __device__ void save_state(DevState* S, const Sha256State& s) {
   for (int k = 0; k < 8; ++k) S->st[k] = s.h[k];
 }
 
-// One challenge: hash st || "GKRC" until the 254-bit candidate is below p.
-// Each attempt is accepted with probability p / 2^254 > 3/4; the bound on
-// attempts only guarantees termination.
-__device__ Fr squeeze(Sha256State& st) {
-  Fr c = fr_zero();
-  for (int attempt = 0; attempt < 4096; ++attempt) {
+// Field products of the serial Fiat-Shamir code: one out-of-line copy keeps
+// the single-thread paths small.
+__device__ __attribute__((noinline)) Fr fr_mul_ni(Fr a, Fr b) { return fr_mul(a, b); }
+__device__ __forceinline__ Fr to_mont_ni(const Fr& a) { return fr_mul_ni(a, fr_r2()); }
+__device__ __forceinline__ Fr from_mont_ni(const Fr& a) { return fr_mul_ni(a, fr_make(1, 0, 0, 0, 0, 0, 0, 0)); }
+
+// g(r) for the degree-2 polynomial with values e0, e1, e2 at t = 0, 1, 2.
+__device__ Fr interp3_ni(const Fr& e0, const Fr& e1, const Fr& e2, const Fr& r) {
+  const Fr d1 = fr_sub(e1, e0);
+  const Fr d2 = fr_add(fr_sub(e2, fr_double(e1)), e0);
+  const Fr rr = fr_mul_ni(fr_mul_ni(r, fr_sub(r, fr_one())), fr_inv2());
+  return fr_add(fr_add(e0, fr_mul_ni(r, d1)), fr_mul_ni(rr, d2));
+}
+
+// The current state as a challenge: rehash with "GKRC" until the 254-bit
+// little-endian value is below p. Each attempt is accepted with probability
+// p / 2^254 > 3/4; the bound on attempts only guarantees termination.
+__device__ Fr accept(Sha256State& st) {
+  Fr c = sha256_to_candidate(st);
+  for (int attempt = 0; attempt < 4096 && !fr_is_canonical(c); ++attempt) {
     uint32_t w[9];
 #pragma unroll
     for (int k = 0; k < 8; ++k) w[k] = st.h[k];
     w[8] = kTagChallenge;
     st = sha256_fixed<9>(w);
     c = sha256_to_candidate(st);
-    if (fr_is_canonical(c)) break;
   }
   return c;
+}
+
+__device__ Fr squeeze(Sha256State& st) {
+  uint32_t w[9];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) w[k] = st.h[k];
+  w[8] = kTagChallenge;
+  st = sha256_fixed<9>(w);
+  return accept(st);
 }
 
 __device__ void absorb_element(Sha256State& st, uint32_t tag, const Fr& canonical) {
@@ -174,13 +197,12 @@ __device__ void absorb_digest(Sha256State& st, const uint32_t* d) {
   st = sha256_fixed<17>(w);
 }
 
-// Round message (e0, e1 = claim - e0, e2): write it to the proof, absorb it,
-// squeeze r, store r and move the claim to g(r).
+// Round message (e0, e1 = claim - e0, e2): write it to the proof, absorb
+// (e0, e2), take the challenge r from the state, store r and move the claim to g(r).
 __device__ void finish_round(DevState* S, const Fr& e0, const Fr& e2, Fr* r_out,
                              uint32_t* msg_out) {
-  const Fr e1 = fr_sub(S->claim, e0);
-  const Fr c0 = fr_from_mont(e0), c1 = fr_from_mont(e1), c2 = fr_from_mont(e2);
-  uint32_t w[33];
+  const Fr c0 = from_mont_ni(e0), c2 = from_mont_ni(e2);
+  uint32_t w[25];
   Sha256State st = load_state(S);
 #pragma unroll
   for (int k = 0; k < 8; ++k) w[k] = st.h[k];
@@ -188,22 +210,26 @@ __device__ void finish_round(DevState* S, const Fr& e0, const Fr& e2, Fr* r_out,
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     w[9 + k] = bswap32(c0.v[k]);
-    w[17 + k] = bswap32(c1.v[k]);
-    w[25 + k] = bswap32(c2.v[k]);
+    w[17 + k] = bswap32(c2.v[k]);
+  }
+  st = sha256_fixed<25>(w);
+  const Fr r = to_mont_ni(accept(st));
+  stf(r_out, 0, r);
+  save_state(S, st);
+  const Fr e1 = fr_sub(S->claim, e0);
+  const Fr c1 = from_mont_ni(e1);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
     msg_out[k] = c0.v[k];
     msg_out[8 + k] = c1.v[k];
     msg_out[16 + k] = c2.v[k];
   }
-  st = sha256_fixed<33>(w);
-  const Fr r = fr_to_mont(squeeze(st));
-  stf(r_out, 0, r);
-  S->claim = fr_interp3(e0, e1, e2, r);
-  save_state(S, st);
+  S->claim = interp3_ni(e0, e1, e2, r);
 }
 
 // A phase's final value: store it, write it to the proof and absorb it.
 __device__ void finish_value(DevState* S, const Fr& v, Fr* v_out, uint32_t* proof_out) {
-  const Fr c = fr_from_mont(v);
+  const Fr c = from_mont_ni(v);
   Sha256State st = load_state(S);
   absorb_element(st, kTagValue, c);
   save_state(S, st);
@@ -308,7 +334,7 @@ __global__ void k_transcript_begin(DevState* S, Words8 seed_state, Words8 circui
 __global__ void k_squeeze(DevState* S, Fr* out, uint32_t count) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   Sha256State st = load_state(S);
-  for (uint32_t k = 0; k < count; ++k) stf(out, k, fr_to_mont(squeeze(st)));
+  for (uint32_t k = 0; k < count; ++k) stf(out, k, to_mont_ni(squeeze(st)));
   save_state(S, st);
 }
 
@@ -323,12 +349,12 @@ __global__ void k_layer_begin(DevState* S, int first, const Fr* vu, const Fr* vv
     return;
   }
   Sha256State st = load_state(S);
-  const Fr a = fr_to_mont(squeeze(st));
-  const Fr b = fr_to_mont(squeeze(st));
+  const Fr a = to_mont_ni(squeeze(st));
+  const Fr b = to_mont_ni(squeeze(st));
   save_state(S, st);
   S->alpha = a;
   S->beta = b;
-  S->claim = fr_add(fr_mul(a, *vu), fr_mul(b, *vv));
+  S->claim = fr_add(fr_mul_ni(a, *vu), fr_mul_ni(b, *vv));
 }
 
 // eq tables: out_j[b] = scale_j * prod_k (bit_k(b) ? r_k : 1 - r_k), bit 1 = MSB.
@@ -367,34 +393,70 @@ __global__ void __launch_bounds__(kBlock)
 //   G[x,c] = sum_{MUL z: x_z=x} T[z,c] W[y_z,c] + sum_{ADD z: x_z=x} T[z,c]
 //   H[x,c] = sum_{ADD z: x_z=x} T[z,c] W[y_z,c]
 // with T[z,c] = aU[z] Cu[c] + bV[z] Cv[c] (the factored eq of both claims).
+__device__ __forceinline__ void phase1_entry(const Fr* __restrict__ W, const uint32_t* __restrict__ xrow,
+                                             const uint2* __restrict__ xent, const Fr* __restrict__ aU,
+                                             const Fr* __restrict__ bV, const Fr* __restrict__ Cu,
+                                             const Fr* __restrict__ Cv, uint32_t n, uint64_t e, Fr& g,
+                                             Fr& h) {
+  const uint64_t mask = (1ull << n) - 1;
+  const uint64_t x = e >> n, c = e & mask;
+  const Fr cu = ldf(Cu, c), cv = ldf(Cv, c);
+  g = fr_zero();
+  h = fr_zero();
+  const uint32_t k1 = xrow[x + 1];
+  for (uint32_t k = xrow[x]; k < k1; ++k) {
+    const uint2 ent = xent[k];
+    const uint64_t z = ent.x, y = ent.y & 0x7fffffffu;
+    const Fr T = fr_add(fr_mul(ldf(aU, z), cu), fr_mul(ldf(bV, z), cv));
+    const Fr tw = fr_mul(T, ldf(W, (y << n) | c));
+    if (ent.y >> 31) {
+      g = fr_add(g, tw);
+    } else {
+      g = fr_add(g, T);
+      h = fr_add(h, tw);
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kBlock)
     k_phase1_init(const Fr* __restrict__ W, Fr* __restrict__ G, Fr* __restrict__ H,
                   const uint32_t* __restrict__ xrow, const uint2* __restrict__ xent,
                   const Fr* __restrict__ aU, const Fr* __restrict__ bV,
                   const Fr* __restrict__ Cu, const Fr* __restrict__ Cv, uint32_t n,
                   uint64_t count) {
-  const uint64_t mask = (1ull << n) - 1;
   for (uint64_t e = gtid(); e < count; e += gstride()) {
-    const uint64_t x = e >> n, c = e & mask;
-    const Fr cu = ldf(Cu, c), cv = ldf(Cv, c);
-    Fr g = fr_zero(), h = fr_zero();
-    const uint32_t k1 = xrow[x + 1];
-    for (uint32_t k = xrow[x]; k < k1; ++k) {
-      const uint2 ent = xent[k];
-      const uint64_t z = ent.x, y = ent.y & 0x7fffffffu;
-      const Fr T = fr_add(fr_mul(ldf(aU, z), cu), fr_mul(ldf(bV, z), cv));
-      const Fr wy = ldf(W, (y << n) | c);
-      const Fr tw = fr_mul(T, wy);
-      if (ent.y >> 31) {
-        g = fr_add(g, tw);
-      } else {
-        g = fr_add(g, T);
-        h = fr_add(h, tw);
-      }
-    }
+    Fr g, h;
+    phase1_entry(W, xrow, xent, aU, bV, Cu, Cv, n, e, g, h);
     stf(G, e, g);
     stf(H, e, h);
   }
+}
+
+// The tables and the first round together: thread b builds entries b and
+// b + half, evaluates the round-1 pair at t = 0, 2, and the last workgroup
+// runs the Fiat-Shamir step.
+__global__ void __launch_bounds__(kBlock)
+    k_phase1_init_round(const Fr* __restrict__ W, Fr* __restrict__ G, Fr* __restrict__ H,
+                        const uint32_t* __restrict__ xrow, const uint2* __restrict__ xent,
+                        const Fr* __restrict__ aU, const Fr* __restrict__ bV,
+                        const Fr* __restrict__ Cu, const Fr* __restrict__ Cv, uint32_t n,
+                        uint64_t half, DevState* S, Fr* partials, Fr* r_out, uint32_t* msg_out) {
+  Fr acc[2] = {fr_zero(), fr_zero()};
+  for (uint64_t b = gtid(); b < half; b += gstride()) {
+    Fr g0, h0, g1, h1;
+    phase1_entry(W, xrow, xent, aU, bV, Cu, Cv, n, b, g0, h0);
+    phase1_entry(W, xrow, xent, aU, bV, Cu, Cv, n, b + half, g1, h1);
+    stf(G, b, g0);
+    stf(H, b, h0);
+    stf(G, b + half, g1);
+    stf(H, b + half, h1);
+    const Fr w0 = ldf(W, b), w1 = ldf(W, b + half);
+    acc[0] = fr_add(acc[0], fr_add(fr_mul(w0, g0), h0));
+    const Fr w2 = fr_sub(fr_double(w1), w0), g2 = fr_sub(fr_double(g1), g0), h2 = fr_sub(fr_double(h1), h0);
+    acc[1] = fr_add(acc[1], fr_add(fr_mul(w2, g2), h2));
+  }
+  if (grid_reduce<2>(acc, partials, &S->counter) && threadIdx.x == 0)
+    finish_round(S, acc[0], acc[1], r_out, msg_out);
 }
 
 // ------------------------------------------------------- round kernels
@@ -581,7 +643,8 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // Column sums over the sub-circuit variables, first stage:
-// part[k][c] = sum_{y in chunk k} EqR[y] W[y,c].
+// part[c * R + k] = sum_{y in chunk k} EqR[y] W[y,c] (R = ychunks chunks of rows),
+// one thread per (column, chunk); each column's partials are contiguous.
 __global__ void __launch_bounds__(kBlock)
     k_local_contract(const Fr* __restrict__ W, const Fr* __restrict__ EqR, Fr* __restrict__ part,
                      uint32_t n, uint64_t rows, uint32_t ychunks) {
@@ -593,23 +656,36 @@ __global__ void __launch_bounds__(kBlock)
   const uint64_t y0 = k * per, y1 = (y0 + per < rows) ? y0 + per : rows;
   Fr acc = fr_zero();
   for (uint64_t y = y0; y < y1; ++y) acc = fr_add(acc, fr_mul(ldf(EqR, y), ldf(W, (y << n) | c)));
-  stf(part, (uint64_t)k * ncop + c, acc);
+  stf(part, c * ychunks + k, acc);
 }
 
-// Second stage: the copy tables of phase 2,
-// Wc[c] = sum_k part[k][c], Fc[c] = U[c] Fa~ + V[c] Fb~, Kc[c] = U[c] Ka~ + V[c] Kb~.
+// Second stage: the copy tables of phase 2. A column's R partials are summed
+// by tpc = min(256, R) threads:
+// Wc[c] = sum_k part[c*R + k], Fc[c] = U[c] Fa~ + V[c] Fb~, Kc[c] = U[c] Ka~ + V[c] Kb~.
 __global__ void __launch_bounds__(kBlock)
     k_copy_tables(const Fr* __restrict__ part, uint32_t ychunks, const Fr* __restrict__ U,
                   const Fr* __restrict__ V, const Fr* fa_f, const Fr* fb_f, const DevState* S,
                   Fr* Wc, Fr* Fc, Fr* Kc, uint64_t ncop) {
-  const uint64_t c = gtid();
-  if (c >= ncop) return;
+  __shared__ Fr sw[kBlock];
+  const uint32_t tpc_log = 31 - __clz(ychunks < kBlock ? ychunks : kBlock);
+  const uint32_t tpc = 1u << tpc_log;
+  const uint64_t c = (uint64_t)blockIdx.x * (kBlock >> tpc_log) + (threadIdx.x >> tpc_log);
+  const uint32_t lane = threadIdx.x & (tpc - 1);
   Fr w = fr_zero();
-  for (uint32_t k = 0; k < ychunks; ++k) w = fr_add(w, ldf(part, (uint64_t)k * ncop + c));
-  const Fr u = ldf(U, c), v = ldf(V, c);
-  stf(Wc, c, w);
-  stf(Fc, c, fr_add(fr_mul(u, *fa_f), fr_mul(v, *fb_f)));
-  stf(Kc, c, fr_add(fr_mul(u, S->ka_f), fr_mul(v, S->kb_f)));
+  if (c < ncop)
+    for (uint32_t k = lane; k < ychunks; k += tpc) w = fr_add(w, ldf(part, c * ychunks + k));
+  sw[threadIdx.x] = w;
+  __syncthreads();
+  for (uint32_t s = tpc / 2; s >= 1; s >>= 1) {
+    if (lane < s) sw[threadIdx.x] = fr_add(sw[threadIdx.x], sw[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (lane == 0 && c < ncop) {
+    const Fr u = ldf(U, c), v = ldf(V, c);
+    stf(Wc, c, sw[threadIdx.x]);
+    stf(Fc, c, fr_add(fr_mul(u, *fa_f), fr_mul(v, *fb_f)));
+    stf(Kc, c, fr_add(fr_mul(u, S->ka_f), fr_mul(v, S->kb_f)));
+  }
 }
 
 // Ka~, Kb~ at the phase-2 local point: dot products with EqR (one workgroup).
@@ -657,54 +733,104 @@ static inline uint32_t grid_for(uint64_t n, uint32_t cap) {
 }
 
 constexpr uint32_t kSweepBlocks = 65535u * 8;  // grid-stride cap of plain sweeps
+constexpr double kE = 32.0;                     // bytes per field element
+
+// Bracket a launch with the optional timing events of its kernel class.
+#define GKR_LAUNCH(cls, bytes, mulmods, stream, ...)            \
+  do {                                                          \
+    const int tok_ = prof_begin(stream);                        \
+    __VA_ARGS__;                                                \
+    if (tok_ >= 0) prof_end(tok_, stream, cls, bytes, mulmods); \
+  } while (0)
 
 void launch_to_mont(const gkr_fr* in, Fr* out, uint64_t n, hipStream_t s) {
-  k_to_mont<<<grid_for(n, kSweepBlocks), kBlock, 0, s>>>(in, out, n);
+  GKR_LAUNCH(PC_CONVERT, 2 * kE * n, (double)n, s,
+             k_to_mont<<<grid_for(n, kSweepBlocks), kBlock, 0, s>>>(in, out, n));
 }
 void launch_from_mont(const Fr* in, gkr_fr* out, uint64_t n, hipStream_t s) {
-  k_from_mont<<<grid_for(n, kSweepBlocks), kBlock, 0, s>>>(in, out, n);
+  GKR_LAUNCH(PC_CONVERT, 2 * kE * n, (double)n, s,
+             k_from_mont<<<grid_for(n, kSweepBlocks), kBlock, 0, s>>>(in, out, n));
 }
-void launch_forward(const Fr* W, Fr* V, const uint2* gates, uint32_t n, uint64_t count, hipStream_t s) {
-  k_forward<<<grid_for(count, kSweepBlocks), kBlock, 0, s>>>(W, V, gates, n, count);
+void launch_forward(const Fr* W, Fr* V, const uint2* gates, uint32_t n, uint64_t count,
+                    uint64_t mul_gates, hipStream_t s) {
+  GKR_LAUNCH(PC_FORWARD, 3 * kE * count, (double)mul_gates, s,
+             k_forward<<<grid_for(count, kSweepBlocks), kBlock, 0, s>>>(W, V, gates, n, count));
 }
 void launch_digest_level(const uint32_t* in, uint64_t nwords, int swap, uint32_t* out,
                          uint64_t nchunks, hipStream_t s) {
-  k_digest_level<<<grid_for(nchunks, kSweepBlocks), kBlock, 0, s>>>(in, nwords, swap, out, nchunks);
+  GKR_LAUNCH(PC_DIGEST, 4.0 * nwords + 32.0 * nchunks, 0.0, s,
+             k_digest_level<<<grid_for(nchunks, kSweepBlocks), kBlock, 0, s>>>(in, nwords, swap, out, nchunks));
 }
 void launch_transcript_begin(DevState* S, const Words8& seed_state, const Words8& circ,
                              const uint32_t* din, const uint32_t* dout, hipStream_t s) {
-  k_transcript_begin<<<1, 64, 0, s>>>(S, seed_state, circ, din, dout);
+  GKR_LAUNCH(PC_TRANSCRIPT, 0.0, 0.0, s, k_transcript_begin<<<1, 64, 0, s>>>(S, seed_state, circ, din, dout));
 }
 void launch_squeeze(DevState* S, Fr* out, uint32_t count, hipStream_t s) {
-  k_squeeze<<<1, 64, 0, s>>>(S, out, count);
+  GKR_LAUNCH(PC_TRANSCRIPT, 0.0, (double)count, s, k_squeeze<<<1, 64, 0, s>>>(S, out, count));
 }
 void launch_layer_begin(DevState* S, int first, const Fr* vu, const Fr* vv, hipStream_t s) {
-  k_layer_begin<<<1, 64, 0, s>>>(S, first, vu, vv);
+  GKR_LAUNCH(PC_TRANSCRIPT, 0.0, 4.0, s, k_layer_begin<<<1, 64, 0, s>>>(S, first, vu, vv));
 }
 void launch_eq_tables(const EqJobs& jobs, hipStream_t s) {
   uint64_t total = 0;
-  for (int j = 0; j < jobs.count; ++j) total += 1ull << jobs.bits[j];
-  k_eq_tables<<<grid_for(total, 1u << 30), kBlock, 0, s>>>(jobs);
+  double mm = 0;
+  for (int j = 0; j < jobs.count; ++j) {
+    total += 1ull << jobs.bits[j];
+    mm += (double)(1ull << jobs.bits[j]) * (jobs.bits[j] + 1);
+  }
+  GKR_LAUNCH(PC_EQ, kE * total, mm, s, k_eq_tables<<<grid_for(total, 1u << 30), kBlock, 0, s>>>(jobs));
 }
 void launch_weighted_sum(const Fr* V, const Fr* A, const Fr* B, uint32_t n, uint64_t count,
                          Fr* partials, uint32_t* counter, Fr* dst, uint32_t max_blocks, hipStream_t s) {
-  k_weighted_sum<<<grid_for(count, max_blocks), kBlock, 0, s>>>(V, A, B, n, count, partials, counter, dst);
+  GKR_LAUNCH(PC_CLAIM, kE * count, 2.0 * count, s,
+             k_weighted_sum<<<grid_for(count, max_blocks), kBlock, 0, s>>>(V, A, B, n, count, partials, counter, dst));
+}
+void launch_phase1_init_round(const Fr* W, Fr* G, Fr* H, const LayerWiring& lw, const Fr* aU,
+                              const Fr* bV, const Fr* Cu, const Fr* Cv, uint32_t n, uint64_t half,
+                              uint64_t gates, DevState* S, Fr* partials, Fr* r_out, uint32_t* msg,
+                              uint32_t max_blocks, hipStream_t s) {
+  GKR_LAUNCH(PC_PHASE1_INIT, kE * (gates + 6.0 * half), 3.0 * gates + 2.0 * half, s,
+             k_phase1_init_round<<<grid_for(half, max_blocks), kBlock, 0, s>>>(W, G, H, lw.xrow, lw.xent, aU, bV, Cu, Cv, n, half, S, partials, r_out, msg));
 }
 void launch_phase1_init(const Fr* W, Fr* G, Fr* H, const LayerWiring& lw, const Fr* aU,
                         const Fr* bV, const Fr* Cu, const Fr* Cv, uint32_t n, uint64_t count,
-                        hipStream_t s) {
-  k_phase1_init<<<grid_for(count, kSweepBlocks), kBlock, 0, s>>>(W, G, H, lw.xrow, lw.xent, aU, bV, Cu, Cv, n, count);
+                        uint64_t gates, hipStream_t s) {
+  GKR_LAUNCH(PC_PHASE1_INIT, kE * (gates + 2.0 * count), 3.0 * gates, s,
+             k_phase1_init<<<grid_for(count, kSweepBlocks), kBlock, 0, s>>>(W, G, H, lw.xrow, lw.xent, aU, bV, Cu, Cv, n, count));
 }
+
+// Algorithmic bytes and products of one round over `half` pairs of NT tables.
+static inline void round_work(int nt, int eval_products, uint64_t half, bool fold, double& bytes,
+                              double& mm) {
+  const double h = (double)half;
+  bytes += fold ? kE * nt * 6.0 * h : kE * nt * 2.0 * h;
+  mm += (fold ? 2.0 * nt * h : 0.0) + eval_products * 2.0 * h;
+}
+
 template <class Form>
 void launch_round(const Tabs<Form::NT>& t, uint64_t half, const Fr* rprev, DevState* S,
                   Fr* partials, Fr* r_out, uint32_t* msg, uint32_t max_blocks, hipStream_t s) {
-  k_round<Form><<<grid_for(half, max_blocks), kBlock, 0, s>>>(t, half, rprev, S, partials, r_out, msg);
+  double bytes = 0, mm = 0;
+  round_work(Form::NT, Form::NT == 3 ? 1 : 2, half, rprev != nullptr, bytes, mm);
+  GKR_LAUNCH(Form::NT == 3 ? PC_ROUND_A : PC_ROUND_B, bytes, mm, s,
+             k_round<Form><<<grid_for(half, max_blocks), kBlock, 0, s>>>(t, half, rprev, S, partials, r_out, msg));
 }
 template <class Form>
 void launch_tail(const Tabs<Form::NT>& t, uint64_t size, const Fr* rpending, uint32_t rounds,
                  DevState* S, Fr* r_out, uint32_t* msg, Fr* final_out, uint32_t* proof_value,
                  hipStream_t s) {
-  k_tail<Form><<<1, kBlock, 0, s>>>(t, size, rpending, rounds, S, r_out, msg, final_out, proof_value);
+  double bytes = 0, mm = 0;
+  bool fold = rpending != nullptr;
+  uint64_t sz = size;
+  for (uint32_t j = 0; j < rounds; ++j) {
+    const uint64_t eval = fold ? sz / 2 : sz;
+    round_work(Form::NT, Form::NT == 3 ? 1 : 2, eval / 2, fold, bytes, mm);
+    fold = true;
+    sz = eval;
+  }
+  if (fold) mm += Form::NT;
+  GKR_LAUNCH(Form::NT == 3 ? PC_TAIL_A : PC_TAIL_B, bytes, mm, s,
+             k_tail<Form><<<1, kBlock, 0, s>>>(t, size, rpending, rounds, S, r_out, msg, final_out, proof_value));
 }
 template void launch_round<FormA>(const Tabs<3>&, uint64_t, const Fr*, DevState*, Fr*, Fr*, uint32_t*, uint32_t, hipStream_t);
 template void launch_round<FormB>(const Tabs<5>&, uint64_t, const Fr*, DevState*, Fr*, Fr*, uint32_t*, uint32_t, hipStream_t);
@@ -713,36 +839,50 @@ template void launch_tail<FormB>(const Tabs<5>&, uint64_t, const Fr*, uint32_t, 
 
 void launch_copy_weights(const Fr* Cu, const Fr* Cv, const Fr* EC, Fr* U, Fr* V, uint64_t ncop,
                          DevState* S, hipStream_t s) {
-  k_copy_weights<<<1, kBlock, 0, s>>>(Cu, Cv, EC, U, V, ncop, S);
+  GKR_LAUNCH(PC_SMALL, 5 * kE * ncop, 2.0 * ncop, s, k_copy_weights<<<1, kBlock, 0, s>>>(Cu, Cv, EC, U, V, ncop, S));
 }
 void launch_phase2_tables(const LayerWiring& lw, const Fr* aU, const Fr* bV, const Fr* EL,
                           const DevState* S, Fr* Fa, Fr* Fb, Fr* Ka, Fr* Kb, Fr* Ks, uint64_t count,
-                          hipStream_t s) {
-  k_phase2_tables<<<grid_for(count, kSweepBlocks), kBlock, 0, s>>>(lw.yrow, lw.yent, aU, bV, EL, S, Fa, Fb, Ka, Kb, Ks, count);
+                          uint64_t gates, hipStream_t s) {
+  GKR_LAUNCH(PC_PHASE2_TABLES, kE * (3.0 * gates + 5.0 * count), 2.0 * gates + 8.0 * count, s,
+             k_phase2_tables<<<grid_for(count, kSweepBlocks), kBlock, 0, s>>>(lw.yrow, lw.yent, aU, bV, EL, S, Fa, Fb, Ka, Kb, Ks, count));
 }
 void launch_copy_contract(const Fr* W, const Fr* U, const Fr* V, Fr* P, Fr* Q, uint32_t n,
                           uint64_t rows, hipStream_t s) {
   const uint32_t tpr_log = n < 8 ? n : 8;
   const uint64_t rows_per_block = kBlock >> tpr_log;
   const uint64_t grid = (rows + rows_per_block - 1) / rows_per_block;
-  k_copy_contract<<<(uint32_t)grid, kBlock, 0, s>>>(W, U, V, P, Q, n, rows);
+  const double elems = (double)(rows << n);
+  GKR_LAUNCH(PC_COPY_CONTRACT, kE * elems, 2.0 * elems, s,
+             k_copy_contract<<<(uint32_t)grid, kBlock, 0, s>>>(W, U, V, P, Q, n, rows));
 }
 void launch_local_contract(const Fr* W, const Fr* EqR, Fr* part, uint32_t n, uint64_t rows,
                            uint32_t ychunks, hipStream_t s) {
   const uint64_t ncop = 1ull << n;
   dim3 grid((uint32_t)((ncop + kBlock - 1) / kBlock), ychunks);
-  k_local_contract<<<grid, kBlock, 0, s>>>(W, EqR, part, n, rows, ychunks);
+  const double elems = (double)(rows << n);
+  GKR_LAUNCH(PC_LOCAL_CONTRACT, kE * elems, elems, s,
+             k_local_contract<<<grid, kBlock, 0, s>>>(W, EqR, part, n, rows, ychunks));
 }
 void launch_copy_tables(const Fr* part, uint32_t ychunks, const Fr* U, const Fr* V, const Fr* fa_f,
                         const Fr* fb_f, const DevState* S, Fr* Wc, Fr* Fc, Fr* Kc, uint64_t ncop,
                         hipStream_t s) {
-  k_copy_tables<<<grid_for(ncop, 1u << 30), kBlock, 0, s>>>(part, ychunks, U, V, fa_f, fb_f, S, Wc, Fc, Kc, ncop);
+  uint32_t tpc_log = 0;
+  while (tpc_log < 8 && (2u << tpc_log) <= ychunks) ++tpc_log;
+  const uint64_t cols_per_block = kBlock >> tpc_log;
+  const uint64_t grid = (ncop + cols_per_block - 1) / cols_per_block;
+  GKR_LAUNCH(PC_SMALL, kE * (ychunks + 5.0) * ncop, 4.0 * ncop, s,
+             k_copy_tables<<<(uint32_t)grid, kBlock, 0, s>>>(part, ychunks, U, V, fa_f, fb_f, S, Wc, Fc, Kc, ncop));
 }
 void launch_local_values(const Fr* EqR, const Fr* Ka, const Fr* Kb, uint64_t rows, DevState* S,
                          hipStream_t s) {
-  k_local_values<<<1, kBlock, 0, s>>>(EqR, Ka, Kb, rows, S);
+  GKR_LAUNCH(PC_SMALL, 3 * kE * rows, 2.0 * rows, s, k_local_values<<<1, kBlock, 0, s>>>(EqR, Ka, Kb, rows, S));
 }
-void launch_state_export(const DevState* S, uint8_t* out, hipStream_t s) { k_state_export<<<1, 64, 0, s>>>(S, out); }
-void launch_state_import(DevState* S, const uint8_t* in, hipStream_t s) { k_state_import<<<1, 64, 0, s>>>(S, in); }
+void launch_state_export(const DevState* S, uint8_t* out, hipStream_t s) {
+  GKR_LAUNCH(PC_SMALL, 0.0, 0.0, s, k_state_export<<<1, 64, 0, s>>>(S, out));
+}
+void launch_state_import(DevState* S, const uint8_t* in, hipStream_t s) {
+  GKR_LAUNCH(PC_SMALL, 0.0, 0.0, s, k_state_import<<<1, 64, 0, s>>>(S, in));
+}
 
 }  // namespace gkr

@@ -44,7 +44,8 @@ struct EqJobs {
 
 void launch_to_mont(const gkr_fr* in, Fr* out, uint64_t n, hipStream_t s);
 void launch_from_mont(const Fr* in, gkr_fr* out, uint64_t n, hipStream_t s);
-void launch_forward(const Fr* W, Fr* V, const uint2* gates, uint32_t n, uint64_t count, hipStream_t s);
+void launch_forward(const Fr* W, Fr* V, const uint2* gates, uint32_t n, uint64_t count,
+                    uint64_t mul_gates, hipStream_t s);
 void launch_digest_level(const uint32_t* in, uint64_t nwords, int swap, uint32_t* out, uint64_t nchunks,
                          hipStream_t s);
 void launch_transcript_begin(DevState* S, const Words8& seed_state, const Words8& circ,
@@ -56,7 +57,11 @@ void launch_weighted_sum(const Fr* V, const Fr* A, const Fr* B, uint32_t n, uint
                          Fr* partials, uint32_t* counter, Fr* dst, uint32_t max_blocks, hipStream_t s);
 void launch_phase1_init(const Fr* W, Fr* G, Fr* H, const LayerWiring& lw, const Fr* aU,
                         const Fr* bV, const Fr* Cu, const Fr* Cv, uint32_t n, uint64_t count,
-                        hipStream_t s);
+                        uint64_t gates, hipStream_t s);
+void launch_phase1_init_round(const Fr* W, Fr* G, Fr* H, const LayerWiring& lw, const Fr* aU,
+                              const Fr* bV, const Fr* Cu, const Fr* Cv, uint32_t n, uint64_t half,
+                              uint64_t gates, DevState* S, Fr* partials, Fr* r_out, uint32_t* msg,
+                              uint32_t max_blocks, hipStream_t s);
 template <class Form>
 void launch_round(const Tabs<Form::NT>& t, uint64_t half, const Fr* rprev, DevState* S,
                   Fr* partials, Fr* r_out, uint32_t* msg, uint32_t max_blocks, hipStream_t s);
@@ -68,7 +73,7 @@ void launch_copy_weights(const Fr* Cu, const Fr* Cv, const Fr* EC, Fr* U, Fr* V,
                          DevState* S, hipStream_t s);
 void launch_phase2_tables(const LayerWiring& lw, const Fr* aU, const Fr* bV, const Fr* EL,
                           const DevState* S, Fr* Fa, Fr* Fb, Fr* Ka, Fr* Kb, Fr* Ks, uint64_t count,
-                          hipStream_t s);
+                          uint64_t gates, hipStream_t s);
 void launch_copy_contract(const Fr* W, const Fr* U, const Fr* V, Fr* P, Fr* Q, uint32_t n,
                           uint64_t rows, hipStream_t s);
 void launch_local_contract(const Fr* W, const Fr* EqR, Fr* part, uint32_t n, uint64_t rows,

@@ -22,3 +22,24 @@ void store_tuning(const Tuning& t) {
 }
 
 }  // namespace gkr
+
+using namespace gkr;
+
+extern "C" int32_t gkr_set_tuning(uint32_t tail_log, uint32_t max_round_blocks) {
+  if (tail_log < 1 || tail_log > 20 || max_round_blocks < 1 || max_round_blocks > kMaxRoundBlocks) {
+    set_error("tuning out of range");
+    return GKR_EINVAL;
+  }
+  Tuning t;
+  t.tail_log = tail_log;
+  t.max_round_blocks = max_round_blocks;
+  store_tuning(t);
+  return GKR_OK;
+}
+
+extern "C" int32_t gkr_get_tuning(uint32_t* tail_log, uint32_t* max_round_blocks) {
+  const Tuning t = current_tuning();
+  if (tail_log) *tail_log = t.tail_log;
+  if (max_round_blocks) *max_round_blocks = t.max_round_blocks;
+  return GKR_OK;
+}

@@ -127,12 +127,24 @@ struct HostTranscript {
       for (int k = 0; k < 8; ++k) w.push_back(bswap32(canon[i].v[k]));
     absorb_words(tag, w.data(), (int)w.size());
   }
-  Fr squeeze() {  // canonical
-    for (;;) {
+  // The state as a challenge, rehashed with "GKRC" until below p (canonical).
+  Fr accept() {
+    Fr c = sha256_to_candidate(st);
+    while (!fr_is_canonical(c)) {
       absorb_words(kTagChallenge, nullptr, 0);
-      Fr c = sha256_to_candidate(st);
-      if (fr_is_canonical(c)) return c;
+      c = sha256_to_candidate(st);
     }
+    return c;
+  }
+  Fr squeeze() {
+    absorb_words(kTagChallenge, nullptr, 0);
+    return accept();
+  }
+  // A round absorbs the values at t = 0 and t = 2; e1 is fixed by the claim.
+  Fr round_challenge(const Fr* e) {
+    const Fr m[2] = {e[0], e[2]};
+    absorb_elements(kTagRound, m, 2);
+    return accept();
   }
 };
 
@@ -214,8 +226,7 @@ extern "C" int32_t gkr_verify(const gkr_circuit* c, const gkr_fr* inputs, const 
           pos += 3;
           const Fr e0 = to_m(e[0]), e1 = to_m(e[1]), e2 = to_m(e[2]);
           if (!fr_eq(fr_add(e0, e1), claim)) accept = false;
-          tr.absorb_elements(kTagRound, e, 3);
-          const Fr r = to_m(tr.squeeze());
+          const Fr r = to_m(tr.round_challenge(e));
           rxy[phase].push_back(r);
           claim = fr_interp3(e0, e1, e2, r);
         }

@@ -17,29 +17,28 @@ GKR_HD uint32_t bswap32(uint32_t x) {
   return (x >> 24) | ((x >> 8) & 0xff00u) | ((x << 8) & 0xff0000u) | (x << 24);
 }
 
-GKR_HD uint32_t sha256_k(int i) {
-  switch (i) {
-    case 0: return 0x428a2f98u; case 1: return 0x71374491u; case 2: return 0xb5c0fbcfu; case 3: return 0xe9b5dba5u;
-    case 4: return 0x3956c25bu; case 5: return 0x59f111f1u; case 6: return 0x923f82a4u; case 7: return 0xab1c5ed5u;
-    case 8: return 0xd807aa98u; case 9: return 0x12835b01u; case 10: return 0x243185beu; case 11: return 0x550c7dc3u;
-    case 12: return 0x72be5d74u; case 13: return 0x80deb1feu; case 14: return 0x9bdc06a7u; case 15: return 0xc19bf174u;
-    case 16: return 0xe49b69c1u; case 17: return 0xefbe4786u; case 18: return 0x0fc19dc6u; case 19: return 0x240ca1ccu;
-    case 20: return 0x2de92c6fu; case 21: return 0x4a7484aau; case 22: return 0x5cb0a9dcu; case 23: return 0x76f988dau;
-    case 24: return 0x983e5152u; case 25: return 0xa831c66du; case 26: return 0xb00327c8u; case 27: return 0xbf597fc7u;
-    case 28: return 0xc6e00bf3u; case 29: return 0xd5a79147u; case 30: return 0x06ca6351u; case 31: return 0x14292967u;
-    case 32: return 0x27b70a85u; case 33: return 0x2e1b2138u; case 34: return 0x4d2c6dfcu; case 35: return 0x53380d13u;
-    case 36: return 0x650a7354u; case 37: return 0x766a0abbu; case 38: return 0x81c2c92eu; case 39: return 0x92722c85u;
-    case 40: return 0xa2bfe8a1u; case 41: return 0xa81a664bu; case 42: return 0xc24b8b70u; case 43: return 0xc76c51a3u;
-    case 44: return 0xd192e819u; case 45: return 0xd6990624u; case 46: return 0xf40e3585u; case 47: return 0x106aa070u;
-    case 48: return 0x19a4c116u; case 49: return 0x1e376c08u; case 50: return 0x2748774cu; case 51: return 0x34b0bcb5u;
-    case 52: return 0x391c0cb3u; case 53: return 0x4ed8aa4au; case 54: return 0x5b9cca4fu; case 55: return 0x682e6ff3u;
-    case 56: return 0x748f82eeu; case 57: return 0x78a5636fu; case 58: return 0x84c87814u; case 59: return 0x8cc70208u;
-    case 60: return 0x90befffau; case 61: return 0xa4506cebu; case 62: return 0xbef9a3f7u; default: return 0xc67178f2u;
-  }
-}
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GKR_SHA_TABLE static __constant__
+#else
+#define GKR_SHA_TABLE static const
+#endif
+
+GKR_SHA_TABLE uint32_t kSha256K[64] = {
+    0x428a2f98u, 0x71374491u, 0xb5c0fbcfu, 0xe9b5dba5u, 0x3956c25bu, 0x59f111f1u, 0x923f82a4u, 0xab1c5ed5u,
+    0xd807aa98u, 0x12835b01u, 0x243185beu, 0x550c7dc3u, 0x72be5d74u, 0x80deb1feu, 0x9bdc06a7u, 0xc19bf174u,
+    0xe49b69c1u, 0xefbe4786u, 0x0fc19dc6u, 0x240ca1ccu, 0x2de92c6fu, 0x4a7484aau, 0x5cb0a9dcu, 0x76f988dau,
+    0x983e5152u, 0xa831c66du, 0xb00327c8u, 0xbf597fc7u, 0xc6e00bf3u, 0xd5a79147u, 0x06ca6351u, 0x14292967u,
+    0x27b70a85u, 0x2e1b2138u, 0x4d2c6dfcu, 0x53380d13u, 0x650a7354u, 0x766a0abbu, 0x81c2c92eu, 0x92722c85u,
+    0xa2bfe8a1u, 0xa81a664bu, 0xc24b8b70u, 0xc76c51a3u, 0xd192e819u, 0xd6990624u, 0xf40e3585u, 0x106aa070u,
+    0x19a4c116u, 0x1e376c08u, 0x2748774cu, 0x34b0bcb5u, 0x391c0cb3u, 0x4ed8aa4au, 0x5b9cca4fu, 0x682e6ff3u,
+    0x748f82eeu, 0x78a5636fu, 0x84c87814u, 0x8cc70208u, 0x90befffau, 0xa4506cebu, 0xbef9a3f7u, 0xc67178f2u};
 
 struct Sha256State {
   uint32_t h[8];
+};
+
+struct Sha256Block {
+  uint32_t w[16];
 };
 
 GKR_HD Sha256State sha256_iv() {
@@ -49,79 +48,50 @@ GKR_HD Sha256State sha256_iv() {
   return s;
 }
 
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GKR_SHA_FN static __device__ __attribute__((noinline))
+#else
+#define GKR_SHA_FN static inline
+#endif
+
 // One compression of a 16-word (big-endian) block into the chaining value.
-GKR_HD void sha256_compress(Sha256State& st, const uint32_t blk[16]) {
-  uint32_t w[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) w[i] = blk[i];
+// The 64 rounds run as four passes of 16 unrolled rounds over a rolling
+// 16-word schedule, so the code stays small (one copy per kernel).
+GKR_SHA_FN Sha256State sha256_compress_v(Sha256State st, Sha256Block blk) {
   uint32_t a = st.h[0], b = st.h[1], c = st.h[2], d = st.h[3];
   uint32_t e = st.h[4], f = st.h[5], g = st.h[6], h = st.h[7];
+  for (int j = 0; j < 64; j += 16) {
 #pragma unroll
-  for (int i = 0; i < 64; ++i) {
-    uint32_t wi;
-    if (i < 16) {
-      wi = w[i];
-    } else {
-      uint32_t w15 = w[(i - 15) & 15], w2 = w[(i - 2) & 15];
-      uint32_t s0 = rotr32(w15, 7) ^ rotr32(w15, 18) ^ (w15 >> 3);
-      uint32_t s1 = rotr32(w2, 17) ^ rotr32(w2, 19) ^ (w2 >> 10);
-      wi = w[i & 15] + s0 + w[(i - 7) & 15] + s1;
-      w[i & 15] = wi;
+    for (int i = 0; i < 16; ++i) {
+      uint32_t wi = blk.w[i];
+      if (j > 0) {
+        const uint32_t w15 = blk.w[(i + 1) & 15], w2 = blk.w[(i + 14) & 15];
+        const uint32_t s0 = rotr32(w15, 7) ^ rotr32(w15, 18) ^ (w15 >> 3);
+        const uint32_t s1 = rotr32(w2, 17) ^ rotr32(w2, 19) ^ (w2 >> 10);
+        wi = blk.w[i] + s0 + blk.w[(i + 9) & 15] + s1;
+        blk.w[i] = wi;
+      }
+      const uint32_t S1 = rotr32(e, 6) ^ rotr32(e, 11) ^ rotr32(e, 25);
+      const uint32_t ch = (e & f) ^ (~e & g);
+      const uint32_t t1 = h + S1 + ch + kSha256K[j + i] + wi;
+      const uint32_t S0 = rotr32(a, 2) ^ rotr32(a, 13) ^ rotr32(a, 22);
+      const uint32_t maj = (a & b) ^ (a & c) ^ (b & c);
+      const uint32_t t2 = S0 + maj;
+      h = g; g = f; f = e; e = d + t1;
+      d = c; c = b; b = a; a = t1 + t2;
     }
-    uint32_t S1 = rotr32(e, 6) ^ rotr32(e, 11) ^ rotr32(e, 25);
-    uint32_t ch = (e & f) ^ (~e & g);
-    uint32_t t1 = h + S1 + ch + sha256_k(i) + wi;
-    uint32_t S0 = rotr32(a, 2) ^ rotr32(a, 13) ^ rotr32(a, 22);
-    uint32_t maj = (a & b) ^ (a & c) ^ (b & c);
-    uint32_t t2 = S0 + maj;
-    h = g; g = f; f = e; e = d + t1;
-    d = c; c = b; b = a; a = t1 + t2;
   }
   st.h[0] += a; st.h[1] += b; st.h[2] += c; st.h[3] += d;
   st.h[4] += e; st.h[5] += f; st.h[6] += g; st.h[7] += h;
+  return st;
 }
 
-// Streaming hasher over 32-bit big-endian words (messages are whole words).
-struct Sha256Words {
-  Sha256State st;
-  uint32_t blk[16];
-  uint32_t fill;    // words in blk
-  uint64_t nwords;  // total words absorbed
-
-  GKR_HD void init() {
-    st = sha256_iv();
-    fill = 0;
-    nwords = 0;
+GKR_HD void sha256_compress(Sha256State& st, const uint32_t blk[16]) {
+  Sha256Block b;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) blk[i] = 0;
-  }
-  GKR_HD void word(uint32_t w) {
-    // Branch-free placement keeps blk in registers when fully unrolled by the caller.
-#pragma unroll
-    for (int i = 0; i < 16; ++i)
-      if ((uint32_t)i == fill) blk[i] = w;
-    ++fill;
-    ++nwords;
-    if (fill == 16) {
-      sha256_compress(st, blk);
-      fill = 0;
-    }
-  }
-  GKR_HD void element(const Fr& canonical) {
-    for (int k = 0; k < 8; ++k) word(bswap32(canonical.v[k]));
-  }
-  GKR_HD void digest(const Sha256State& d) {
-    for (int k = 0; k < 8; ++k) word(d.h[k]);
-  }
-  GKR_HD Sha256State finish() {
-    uint64_t bits = nwords * 32;
-    word(0x80000000u);
-    while (fill != 14) word(0);
-    word((uint32_t)(bits >> 32));
-    word((uint32_t)bits);
-    return st;
-  }
-};
+  for (int i = 0; i < 16; ++i) b.w[i] = blk[i];
+  st = sha256_compress_v(st, b);
+}
 
 // A digest's bytes (big-endian words h[0..7]) read as a little-endian integer,
 // masked to 254 bits: the candidate of one squeeze attempt, as canonical limbs.

@@ -1,0 +1,61 @@
+"""Write the stored expected proofs under tests/golden/ from the CPU oracle.
+
+Only the oracle and the seeded generator are used. Each file records the
+workload, the SHA-256 of the outputs and of the proof, and the proof itself
+(hex) for the smaller cases.
+
+    python tests/golden/make_golden.py c1 c2 c3slice
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import gkr_synth as gs  # noqa: E402
+from oracle import circuit as oc  # noqa: E402
+from oracle import prover as op  # noqa: E402
+from oracle.field import encode_all  # noqa: E402
+
+CASES = {
+    "c1": (gs.plain_c1, True),
+    "c2": (gs.data_parallel_c2, True),
+    # the single-worker share's sub-circuit (depth 24, 2^14 gates, 30% MUL) with 2^4 copies
+    "c3slice": (lambda: gs.copy_slice(gs.worker_share_c3(), 4), True),
+}
+
+
+def make(name):
+    spec = CASES[name][0]()
+    t0 = time.time()
+    wiring = gs.make_wiring(spec)
+    inputs = gs.elements_to_ints(gs.make_inputs(spec))
+    c = oc.Circuit.from_synth(spec, wiring)
+    pt = op.prove(c, inputs, spec.seed)
+    proof = pt.proof_bytes()
+    rec = {
+        "workload": name,
+        "depth": spec.depth,
+        "log_copies": spec.log_copies,
+        "log_sub_width": list(spec.log_sub_width),
+        "mu": list(spec.mu),
+        "seed": spec.seed,
+        "outputs_sha256": hashlib.sha256(encode_all(pt.outputs)).hexdigest(),
+        "proof_sha256": hashlib.sha256(proof).hexdigest(),
+        "proof_len": len(proof),
+        "oracle_seconds": round(time.time() - t0, 1),
+        "writer": "tests/golden/make_golden.py (CPU oracle)",
+    }
+    if CASES[name][1]:
+        rec["proof_hex"] = proof.hex()
+    with open(os.path.join(HERE, "%s_proof.json" % name), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(name, "done in %.1f s" % (time.time() - t0), flush=True)
+
+
+if __name__ == "__main__":
+    for n in sys.argv[1:] or ["c1"]:
+        make(n)

@@ -15,15 +15,17 @@ def test_sha256_fips_vectors():
 
 
 def test_tree_digest_structure():
-    one = bytes(range(256)) * 32  # exactly one chunk
+    one = bytes(range(256)) * 4  # exactly one chunk
     assert len(one) == T.CHUNK_BYTES
     assert T.tree_digest(one) == hashlib.sha256(one).digest()
     two = one + b"\x07" * 100  # two chunks, the second short
     expect = hashlib.sha256(hashlib.sha256(one).digest() + hashlib.sha256(b"\x07" * 100).digest()).digest()
     assert T.tree_digest(two) == expect
-    # 257 chunks -> 257 digests (8224 bytes) -> two chunks -> one digest
-    big = b"\x01" * (T.CHUNK_BYTES * 257)
+    # CHUNK/32 + 1 leaves -> that many digests (one chunk plus 32 bytes) -> two digests -> root
+    leaves = T.CHUNK_BYTES // 32 + 1
+    big = b"\x01" * (T.CHUNK_BYTES * leaves)
     lvl1 = b"".join(hashlib.sha256(big[i:i + T.CHUNK_BYTES]).digest() for i in range(0, len(big), T.CHUNK_BYTES))
+    assert len(lvl1) == T.CHUNK_BYTES + 32
     lvl2 = hashlib.sha256(lvl1[:T.CHUNK_BYTES]).digest() + hashlib.sha256(lvl1[T.CHUNK_BYTES:]).digest()
     assert T.tree_digest(big) == hashlib.sha256(lvl2).digest()
 
@@ -43,6 +45,20 @@ def test_transcript_chain_by_hand():
         if cand < F.P:
             break
     assert v == cand and tr.state == st
+
+
+def test_round_challenge_by_hand():
+    tr = T.Transcript(8)
+    st = tr.state
+    e0, e2 = 12345, F.P - 7
+    r = tr.round_challenge(e0, e2)
+    st = hashlib.sha256(st + b"GKRR" + e0.to_bytes(32, "little") + e2.to_bytes(32, "little")).digest()
+    while int.from_bytes(st, "little") % (1 << 254) >= F.P:
+        st = hashlib.sha256(st + b"GKRC").digest()
+    assert r == int.from_bytes(st, "little") % (1 << 254) and tr.state == st
+    # the challenge depends on both absorbed values
+    t2 = T.Transcript(8)
+    assert t2.round_challenge(e0, e2 - 1) != r
 
 
 def test_squeeze_is_uniform_looking_and_in_range():
