@@ -111,6 +111,79 @@ def cpu_baseline(spec, budget_s=20.0):
                       % (sl.log_copies, spec.log_copies, sl.gate_layers, dt)}
 
 
+def batched_comparison(gkr, steps, warmup):
+    """64 uneven jobs: sequential plain proofs, sequential graph replays, one batched launch."""
+    import torch
+    specs = gs.batch_jobs_c4()
+    jobs = []
+    for spec in specs:
+        c = gkr.Circuit.from_synth(spec, gs.make_wiring(spec))
+        d_in = gkr.device_elements(gs.make_inputs(spec))
+        out = torch.zeros((1 << c.s(0), 8), dtype=torch.int32, device="cuda")
+        proof = gkr.alloc_bytes(c.proof_bytes)
+        ws = gkr.alloc_bytes(c.workspace_bytes)
+        jobs.append((spec, c, d_in, out, proof, ws))
+    gates = sum(c.gate_layers for _, c, *_ in jobs)
+
+    def plain():
+        for spec, c, d_in, out, proof, ws in jobs:
+            gkr.prove_circuit(c, d_in, spec.seed, out, proof, ws)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    t_plain = timed(plain)
+    # the same sequential proofs captured once per job in HIP graphs, then replayed
+    graphs = []
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for spec, c, d_in, out, proof, ws in jobs:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=stream):
+                gkr.prove_circuit(c, d_in, spec.seed, out, proof, ws, stream=stream)
+            graphs.append(g)
+    torch.cuda.synchronize()
+
+    def graph_replay():
+        for g in graphs:
+            g.replay()
+
+    t_graph = timed(graph_replay)
+    plans = [gkr.Plan(gkr.make_job(c, d_in, spec.seed, out, proof, ws)) for spec, c, d_in, out, proof, ws in jobs]
+    ctl = torch.zeros(4, dtype=torch.int32, device="cuda")
+
+    def batched():
+        for p in plans:
+            p.reset()
+        gkr.run_batch(plans, ctl)
+
+    t_batch = timed(batched)
+    # the batched proofs are checked against the oracle digests when available
+    exact = None
+    gp = os.path.join(ROOT, "tests", "golden", "c4_batch.json")
+    if os.path.exists(gp):
+        with open(gp) as f:
+            gold = json.load(f)["jobs"]
+        exact = all(hashlib.sha256(bytes(proof[: c.proof_bytes].cpu().numpy().tobytes())).hexdigest()
+                    == gold[k]["proof_sha256"] for k, (spec, c, d_in, out, proof, ws) in enumerate(jobs))
+    return {
+        "workload": "64 uneven jobs: log2 gates/layer in [10,18], depth in [8,32], 2^4..2^10 copies",
+        "gate_layers": gates,
+        "plain_sequential": {"ms": round(t_plain * 1e3, 3), "field_gates_per_s": round(gates / t_plain, 1)},
+        "graph_sequential": {"ms": round(t_graph * 1e3, 3), "field_gates_per_s": round(gates / t_graph, 1)},
+        "batched_persistent": {"ms": round(t_batch * 1e3, 3), "field_gates_per_s": round(gates / t_batch, 1)},
+        "speedup_vs_plain": round(t_plain / t_batch, 2),
+        "bit_exact_vs_oracle_golden": exact,
+    }
+
+
 def golden_digest(workload):
     p = os.path.join(ROOT, "tests", "golden", "%s_proof.json" % workload)
     if not os.path.exists(p):
@@ -128,6 +201,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--mode", default="plain", choices=["plain", "batched"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build proves one worker's share on a single MI355X "
@@ -136,6 +210,17 @@ def main():
 
     import torch
     from paper_2404_10404_amd import gkr
+
+    if args.mode == "batched":
+        res = batched_comparison(gkr, args.steps, args.warmup)
+        line = {"metric": "GKR prover field-gates/sec, batched persistent launch vs plain per-job launches",
+                "value": res["batched_persistent"]["field_gates_per_s"], "unit": "field-gates/s", "n_gpus": 1,
+                "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["batched_persistent"]["ms"],
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "u32 (BN254 Fr, exact modular integer arithmetic)", "data": "synthetic",
+                "config": {"workload": res["workload"]}, "batched": res}
+        print(json.dumps(line), flush=True)
+        return
 
     spec = WORKLOADS[args.workload][0]()
     wiring = gs.make_wiring(spec)

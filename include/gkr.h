@@ -165,6 +165,56 @@ int32_t gkr_prove_layer(const gkr_circuit* circuit, uint32_t layer, const gkr_fr
                         size_t ws_bytes, void* stream);
 
 /*
+ * Batched proving (many proofs at once in one persistent kernel).
+ *
+ * A job names a circuit, its inputs, seed and output/proof/workspace buffers
+ * (the buffers gkr_prove_circuit takes). gkr_plan_create records the job's
+ * proof as a step program in device memory (allocates and copies: call it
+ * outside any timed or captured region). gkr_run_batch then runs 1..64 plans
+ * together: resident workgroups take tiles of whichever plan has work, so the
+ * serial Fiat-Shamir steps of one proof overlap the table sweeps of the
+ * others. A run allocates nothing and copies nothing between host and device
+ * (graph-capturable). Each plan's proof bytes are identical to its
+ * gkr_prove_circuit bytes. Buffers of different jobs must not overlap.
+ */
+typedef struct {
+  const gkr_circuit* circuit;
+  const gkr_fr* d_inputs;
+  uint64_t seed;
+  gkr_fr* d_outputs;
+  uint8_t* d_proof;
+  size_t proof_cap;
+  void* d_ws;
+  size_t ws_bytes;
+} gkr_job;
+
+typedef struct gkr_plan gkr_plan;
+
+/* Record a job's proof program (GKR_EINVAL, GKR_EBUFSZ, GKR_ENOMEM, GKR_EDEVICE). */
+int32_t gkr_plan_create(const gkr_job* job, gkr_plan** out);
+void gkr_plan_destroy(gkr_plan* plan);
+/* Queue a reset of the plan's progress so its next run proves from the start. */
+int32_t gkr_plan_reset(gkr_plan* plan, void* stream);
+/*
+ * Queue one persistent launch over `n` (1..64) distinct plans. d_ctl: 4 device
+ * words owned by this call until the stream reaches its end ([0] plans
+ * finished in this launch, [1] stop flag, [2] steps completed). workgroups:
+ * resident workgroups (0 = fill the device). step_budget > 0 stops the launch
+ * after about that many completed steps; stop_on_finish stops it when any plan
+ * finishes. A stopped launch leaves every plan resumable: run it again to
+ * continue. Plans already finished are skipped.
+ */
+int32_t gkr_run_batch(gkr_plan* const* plans, uint32_t n, uint32_t* d_ctl, uint32_t workgroups,
+                      uint32_t step_budget, uint32_t stop_on_finish, void* stream);
+/* Steps completed so far and the plan's step count (synchronous device read). */
+int32_t gkr_plan_progress(const gkr_plan* plan, uint32_t* done_steps, uint32_t* total_steps);
+/*
+ * Convenience: plans for `n` jobs, persistent runs of up to 64 plans each on
+ * `stream`, then a synchronisation and cleanup. Allocates; synchronous.
+ */
+int32_t gkr_prove_batch(const gkr_job* jobs, uint32_t n, void* stream);
+
+/*
  * Verifier (host only, synchronous). inputs / outputs / proof are host
  * buffers. Returns 1 (accept), 0 (reject) or a negative status for malformed
  * arguments: GKR_EINVAL for a proof of the wrong length or any element >= p.

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "gkr_kernels.hpp"
+#include "gkr_program.hpp"
 #include "gkr_tuning.hpp"
 
 namespace gkr {
@@ -164,10 +165,45 @@ Workspace bind_workspace(const gkr_circuit& c, void* base) {
   return w;
 }
 
-// ------------------------------------------------------------------ proof pieces
+// ------------------------------------------------------------------ step builders
 
-static void run_digest(const gkr_fr* vec, uint64_t nelem, uint32_t* final_out, const Workspace& w,
-                       hipStream_t s) {
+constexpr uint32_t kSweepTiles = 65535u * 8;  // grid-stride cap of plain sweeps
+constexpr double kE = 32.0;                   // bytes per field element
+
+static uint32_t tiles_for(uint64_t n, uint32_t cap) {
+  uint64_t g = (n + kBlock - 1) / kBlock;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (uint32_t)g;
+}
+
+static Step mk(uint32_t type, uint32_t ntiles) {
+  Step st;
+  memset(&st, 0, sizeof(st));
+  st.type = type;
+  st.ntiles = ntiles < 1 ? 1 : ntiles;
+  return st;
+}
+
+void Program::to_mont(const gkr_fr* in, Fr* out, uint64_t n) {
+  Step st = mk(ST_TO_MONT, tiles_for(n, kSweepTiles));
+  st.p[0] = in; st.p[1] = out; st.q[0] = n;
+  st.bytes = 2 * kE * n; st.mulmods = (double)n;
+  steps.push_back(st);
+}
+void Program::from_mont(const Fr* in, gkr_fr* out, uint64_t n) {
+  Step st = mk(ST_FROM_MONT, tiles_for(n, kSweepTiles));
+  st.p[0] = in; st.p[1] = out; st.q[0] = n;
+  st.bytes = 2 * kE * n; st.mulmods = (double)n;
+  steps.push_back(st);
+}
+void Program::forward(const Fr* W, Fr* V, const uint2* gates, uint32_t n, uint64_t count, uint64_t mul_gates) {
+  Step st = mk(ST_FORWARD, tiles_for(count, kSweepTiles));
+  st.p[0] = W; st.p[1] = V; st.p[2] = gates; st.u[0] = n; st.q[0] = count;
+  st.bytes = 3 * kE * count; st.mulmods = (double)mul_gates;
+  steps.push_back(st);
+}
+void Program::digest(const gkr_fr* vec, uint64_t nelem, uint32_t* final_out, const Workspace& w) {
   const uint32_t* in = reinterpret_cast<const uint32_t*>(vec);
   uint64_t nwords = nelem * 8;
   int swap = 1;
@@ -176,7 +212,10 @@ static void run_digest(const gkr_fr* vec, uint64_t nelem, uint32_t* final_out, c
   for (;;) {
     const uint64_t nchunks = (nwords + kChunkWords - 1) / kChunkWords;
     uint32_t* out = (nchunks == 1) ? final_out : bufs[which];
-    launch_digest_level(in, nwords, swap, out, nchunks, s);
+    Step st = mk(ST_DIGEST, tiles_for(nchunks, kSweepTiles));
+    st.p[0] = in; st.p[1] = out; st.q[0] = nwords; st.q[1] = nchunks; st.u[0] = swap;
+    st.bytes = 4.0 * nwords + 32.0 * nchunks;
+    steps.push_back(st);
     if (nchunks == 1) break;
     in = out;
     nwords = nchunks * 8;
@@ -184,116 +223,306 @@ static void run_digest(const gkr_fr* vec, uint64_t nelem, uint32_t* final_out, c
     which ^= 1;
   }
 }
+void Program::transcript_begin(DevState* S, const Words8& seed_state, const uint32_t* circ,
+                               const uint32_t* din, const uint32_t* dout) {
+  Step st = mk(ST_TRANSCRIPT_BEGIN, 1);
+  st.p[0] = S; st.p[1] = din; st.p[2] = dout;
+  memcpy(st.w, seed_state.w, 32);
+  memcpy(st.w + 8, circ, 32);
+  steps.push_back(st);
+}
+void Program::squeeze(DevState* S, Fr* out, uint32_t count) {
+  Step st = mk(ST_SQUEEZE, 1);
+  st.p[0] = S; st.p[1] = out; st.u[0] = count; st.mulmods = count;
+  steps.push_back(st);
+}
+void Program::layer_begin(DevState* S, bool first, const Fr* vu, const Fr* vv) {
+  Step st = mk(ST_LAYER_BEGIN, 1);
+  st.p[0] = S; st.p[1] = vu; st.p[2] = vv; st.u[0] = first ? 1 : 0; st.mulmods = 4;
+  steps.push_back(st);
+}
+void Program::eq(int count, const uint32_t* bits, const Fr* const* points, const Fr* const* scales, Fr* const* outs) {
+  uint64_t total = 0;
+  double mm = 0;
+  Step st = mk(ST_EQ, 1);
+  for (int j = 0; j < count; ++j) {
+    st.u[j] = bits[j];
+    st.p[j] = points[j];
+    st.p[4 + j] = scales[j];
+    st.p[8 + j] = outs[j];
+    total += 1ull << bits[j];
+    mm += (double)(1ull << bits[j]) * (bits[j] + 1);
+  }
+  st.u[4] = count;
+  st.ntiles = tiles_for(total, 1u << 30);
+  st.bytes = kE * total; st.mulmods = mm;
+  steps.push_back(st);
+}
+void Program::wsum(const Fr* V, const Fr* A, const Fr* B, uint32_t n, uint64_t count, Fr* partials,
+                   DevState* S, Fr* dst, const Tuning& tun) {
+  Step st = mk(ST_WSUM, tiles_for(count, tun.max_round_blocks));
+  st.p[0] = V; st.p[1] = A; st.p[2] = B; st.p[3] = partials; st.p[4] = S; st.p[5] = dst;
+  st.u[0] = n; st.q[0] = count;
+  st.bytes = kE * count; st.mulmods = 2.0 * count;
+  steps.push_back(st);
+}
+static void p1_common(Step& st, const Fr* W, Fr* G, Fr* H, const LayerWiring& lw, const Fr* aU,
+                      const Fr* bV, const Fr* Cu, const Fr* Cv, uint32_t n) {
+  st.p[0] = W; st.p[1] = G; st.p[2] = H; st.p[3] = lw.xrow; st.p[4] = lw.xent;
+  st.p[5] = aU; st.p[6] = bV; st.p[7] = Cu; st.p[8] = Cv; st.u[0] = n;
+}
+void Program::p1_init(const Fr* W, Fr* G, Fr* H, const LayerWiring& lw, const Fr* aU, const Fr* bV,
+                      const Fr* Cu, const Fr* Cv, uint32_t n, uint64_t count, uint64_t gates) {
+  Step st = mk(ST_P1_INIT, tiles_for(count, kSweepTiles));
+  p1_common(st, W, G, H, lw, aU, bV, Cu, Cv, n);
+  st.q[0] = count;
+  st.bytes = kE * (gates + 2.0 * count); st.mulmods = 3.0 * gates;
+  steps.push_back(st);
+}
+void Program::p1_init_round(const Fr* W, Fr* G, Fr* H, const LayerWiring& lw, const Fr* aU,
+                            const Fr* bV, const Fr* Cu, const Fr* Cv, uint32_t n, uint64_t half,
+                            uint64_t gates, DevState* S, Fr* partials, Fr* r_out, uint32_t* msg,
+                            const Tuning& tun) {
+  Step st = mk(ST_P1_INIT_ROUND, tiles_for(half, tun.max_round_blocks));
+  p1_common(st, W, G, H, lw, aU, bV, Cu, Cv, n);
+  st.q[0] = half;
+  st.p[9] = S; st.p[10] = partials; st.p[11] = r_out; st.p[12] = msg;
+  st.bytes = kE * (gates + 6.0 * half); st.mulmods = 3.0 * gates + 2.0 * half;
+  steps.push_back(st);
+}
 
-// The round schedule of one phase over FormA/FormB tables: grid-wide rounds
-// while the evaluated table exceeds the tail size, then one workgroup.
-template <class Form>
-static void run_phase(Tabs<Form::NT> t, uint32_t nrounds, DevState* S, Fr* partials, Fr* r_out,
-                      uint32_t* msg, Fr* final_out, uint32_t* proof_value, const Tuning& tun,
-                      hipStream_t s, uint32_t first_round = 0) {
-  // first_round > 0: the rounds before it were already evaluated (their
-  // challenge is pending) and the tables have 2^(nrounds - first_round + 1) entries.
+// Algorithmic bytes and products of one round over `half` pairs of NT tables
+// (eval_products products per evaluation point).
+static void round_work(int nt, int eval_products, uint64_t half, bool fold, double& bytes, double& mm) {
+  const double h = (double)half;
+  bytes += fold ? kE * nt * 6.0 * h : kE * nt * 2.0 * h;
+  mm += (fold ? 2.0 * nt * h : 0.0) + eval_products * 2.0 * h;
+}
+
+template <int NT>
+void Program::round(const Fr* const* src, Fr* const* dst, uint64_t half, const Fr* rprev, DevState* S,
+                    Fr* partials, Fr* r_out, uint32_t* msg, const Tuning& tun) {
+  using R = RoundPtrs<NT>;
+  Step st = mk(NT == 3 ? ST_ROUND_A : ST_ROUND_B, tiles_for(half, tun.max_round_blocks));
+  for (int k = 0; k < NT; ++k) {
+    st.p[k] = src[k];
+    st.p[NT + k] = dst[k];
+  }
+  st.p[R::kR] = rprev; st.p[R::kS] = S; st.p[R::kPart] = partials; st.p[R::kROut] = r_out; st.p[R::kMsg] = msg;
+  st.q[0] = half;
+  round_work(NT, NT == 3 ? 1 : 2, half, rprev != nullptr, st.bytes, st.mulmods);
+  steps.push_back(st);
+}
+template <int NT>
+void Program::tail(const Fr* const* src, Fr* const* dst, uint64_t size, const Fr* rpending, uint32_t rounds,
+                   DevState* S, Fr* r_out, uint32_t* msg, Fr* final_out, uint32_t* proof_value) {
+  Step st = mk(NT == 3 ? ST_TAIL_A : ST_TAIL_B, 1);
+  for (int k = 0; k < NT; ++k) {
+    st.p[k] = src[k];
+    st.p[NT + k] = dst[k];
+  }
+  st.p[2 * NT] = rpending; st.p[2 * NT + 1] = S; st.p[2 * NT + 2] = r_out; st.p[2 * NT + 3] = msg;
+  st.p[2 * NT + 4] = final_out; st.p[2 * NT + 5] = proof_value;
+  st.q[0] = size; st.u[0] = rounds;
+  bool fold = rpending != nullptr;
+  uint64_t sz = size;
+  for (uint32_t j = 0; j < rounds; ++j) {
+    const uint64_t ev = fold ? sz / 2 : sz;
+    round_work(NT, NT == 3 ? 1 : 2, ev / 2, fold, st.bytes, st.mulmods);
+    fold = true;
+    sz = ev;
+  }
+  if (fold) st.mulmods += NT;
+  steps.push_back(st);
+}
+void Program::copy_weights(const Fr* Cu, const Fr* Cv, const Fr* EC, Fr* U, Fr* V, uint64_t ncop, DevState* S) {
+  Step st = mk(ST_COPY_WEIGHTS, 1);
+  st.p[0] = Cu; st.p[1] = Cv; st.p[2] = EC; st.p[3] = U; st.p[4] = V; st.p[5] = S; st.q[0] = ncop;
+  st.bytes = 5 * kE * ncop; st.mulmods = 2.0 * ncop;
+  steps.push_back(st);
+}
+void Program::p2_tables(const LayerWiring& lw, const Fr* aU, const Fr* bV, const Fr* EL, const DevState* S,
+                        Fr* Fa, Fr* Fb, Fr* Ka, Fr* Kb, Fr* Ks, uint64_t count, uint64_t gates) {
+  Step st = mk(ST_P2_TABLES, tiles_for(count, kSweepTiles));
+  st.p[0] = lw.yrow; st.p[1] = lw.yent; st.p[2] = aU; st.p[3] = bV; st.p[4] = EL; st.p[5] = S;
+  st.p[6] = Fa; st.p[7] = Fb; st.p[8] = Ka; st.p[9] = Kb; st.p[10] = Ks; st.q[0] = count;
+  st.bytes = kE * (3.0 * gates + 5.0 * count); st.mulmods = 2.0 * gates + 8.0 * count;
+  steps.push_back(st);
+}
+void Program::copy_contract(const Fr* W, const Fr* U, const Fr* V, Fr* Pt, Fr* Qt, uint32_t n, uint64_t rows) {
+  const uint32_t tpr_log = n < 8 ? n : 8;
+  const uint64_t rows_per_tile = kBlock >> tpr_log;
+  Step st = mk(ST_COPY_CONTRACT, (uint32_t)std::min<uint64_t>((rows + rows_per_tile - 1) / rows_per_tile, kSweepTiles));
+  st.p[0] = W; st.p[1] = U; st.p[2] = V; st.p[3] = Pt; st.p[4] = Qt; st.u[0] = n; st.q[0] = rows;
+  const double elems = (double)(rows << n);
+  st.bytes = kE * elems; st.mulmods = 2.0 * elems;
+  steps.push_back(st);
+}
+void Program::local_contract(const Fr* W, const Fr* EqR, Fr* part, uint32_t n, uint64_t rows, uint32_t R) {
+  const uint64_t xb = ((1ull << n) + kBlock - 1) / kBlock;
+  Step st = mk(ST_LOCAL_CONTRACT, (uint32_t)std::min<uint64_t>(xb * R, kSweepTiles));
+  st.p[0] = W; st.p[1] = EqR; st.p[2] = part; st.u[0] = n; st.u[1] = R; st.q[0] = rows;
+  const double elems = (double)(rows << n);
+  st.bytes = kE * elems; st.mulmods = elems;
+  steps.push_back(st);
+}
+void Program::copy_tables(const Fr* part, uint32_t R, const Fr* U, const Fr* V, const Fr* fa_f, const Fr* fb_f,
+                          const DevState* S, Fr* Wc, Fr* Fc, Fr* Kc, uint64_t ncop) {
+  uint32_t tpc_log = 0;
+  while (tpc_log < 8 && (2u << tpc_log) <= R) ++tpc_log;
+  const uint64_t cols_per_tile = kBlock >> tpc_log;
+  Step st = mk(ST_COPY_TABLES, (uint32_t)std::min<uint64_t>((ncop + cols_per_tile - 1) / cols_per_tile, kSweepTiles));
+  st.p[0] = part; st.p[1] = U; st.p[2] = V; st.p[3] = fa_f; st.p[4] = fb_f; st.p[5] = S;
+  st.p[6] = Wc; st.p[7] = Fc; st.p[8] = Kc; st.u[0] = R; st.q[0] = ncop;
+  st.bytes = kE * (R + 5.0) * ncop; st.mulmods = 4.0 * ncop;
+  steps.push_back(st);
+}
+void Program::local_values(const Fr* EqR, const Fr* Ka, const Fr* Kb, uint64_t rows, DevState* S) {
+  Step st = mk(ST_LOCAL_VALUES, 1);
+  st.p[0] = EqR; st.p[1] = Ka; st.p[2] = Kb; st.p[3] = S; st.q[0] = rows;
+  st.bytes = 3 * kE * rows; st.mulmods = 2.0 * rows;
+  steps.push_back(st);
+}
+void Program::state_export(const DevState* S, uint8_t* out) {
+  Step st = mk(ST_STATE_EXPORT, 1);
+  st.p[0] = S; st.p[1] = out;
+  steps.push_back(st);
+}
+void Program::state_import(DevState* S, const uint8_t* in) {
+  Step st = mk(ST_STATE_IMPORT, 1);
+  st.p[0] = S; st.p[1] = in;
+  steps.push_back(st);
+}
+
+void Program::run(hipStream_t s) const {
+  for (const Step& st : steps) launch_step(st, s);
+}
+
+// ------------------------------------------------------------------ proof programs
+
+// The round schedule of one phase over NT-table forms: grid-wide rounds while
+// the evaluated table exceeds the tail size, then one workgroup. With
+// first_round > 0 the rounds before it were already evaluated (their
+// challenge is pending) and the tables have 2^(nrounds - first_round + 1) entries.
+template <int NT>
+static void emit_phase(Program& pg, const Fr* const* src0, Fr* const* dst, uint32_t nrounds, DevState* S,
+                       Fr* partials, Fr* r_out, uint32_t* msg, Fr* final_out, uint32_t* proof_value,
+                       const Tuning& tun, uint32_t first_round = 0) {
+  const Fr* src[NT];
+  for (int k = 0; k < NT; ++k) src[k] = src0[k];
   uint64_t eval = 1ull << (nrounds - first_round);
   uint32_t j = first_round;
   const Fr* pending = first_round ? r_out + first_round - 1 : nullptr;
   while (j < nrounds && eval > (1ull << tun.tail_log)) {
-    launch_round<Form>(t, eval / 2, pending, S, partials, r_out + j, msg + 24 * j,
-                       tun.max_round_blocks, s);
+    pg.round<NT>(src, dst, eval / 2, pending, S, partials, r_out + j, msg + 24 * j, tun);
     if (pending) {
-      for (int k = 0; k < Form::NT; ++k) t.src[k] = t.dst[k];
+      for (int k = 0; k < NT; ++k) src[k] = dst[k];
     }
     pending = r_out + j;
     ++j;
     eval /= 2;
   }
   const uint64_t size = pending ? 2 * eval : eval;
-  launch_tail<Form>(t, size, pending, nrounds - j, S, r_out + j, msg + 24 * j, final_out,
-                    proof_value, s);
+  pg.tail<NT>(src, dst, size, pending, nrounds - j, S, r_out + j, msg + 24 * j, final_out, proof_value);
 }
 
 // One gate layer (A3-A7). W = V_{i+1} in Montgomery form; u, v points of
 // layer i (s_i entries each, v = u on layer 0); vu, vv the claimed values.
-static void run_layer(const gkr_circuit& c, uint32_t i, const Workspace& w, const Fr* W,
-                      const Fr* u, const Fr* v, const Fr* vu, const Fr* vv, Fr* rx, Fr* ry,
-                      uint32_t* proof, const Tuning& tun, hipStream_t s) {
+void emit_layer(Program& pg, const gkr_circuit& c, uint32_t i, const Workspace& w, const Fr* W, const Fr* u,
+                const Fr* v, const Fr* vu, const Fr* vv, Fr* rx, Fr* ry, uint32_t* proof, const Tuning& tun) {
   const uint32_t n = c.n, sg = c.sigma[i], sg1 = c.sigma[i + 1], s1 = c.s(i + 1);
   DevState* S = w.state;
-  launch_layer_begin(S, i == 0, vu, vv, s);
-
-  EqJobs e1{};
-  e1.count = 4;
-  e1.bits[0] = sg; e1.point[0] = u; e1.scale[0] = &S->alpha; e1.out[0] = w.aU;
-  e1.bits[1] = sg; e1.point[1] = v; e1.scale[1] = &S->beta; e1.out[1] = w.bV;
-  e1.bits[2] = n; e1.point[2] = u + sg; e1.scale[2] = nullptr; e1.out[2] = w.Cu;
-  e1.bits[3] = n; e1.point[3] = v + sg; e1.scale[3] = nullptr; e1.out[3] = w.Cv;
-  launch_eq_tables(e1, s);
-
+  pg.layer_begin(S, i == 0, vu, vv);
+  {
+    const uint32_t bits[4] = {sg, sg, n, n};
+    const Fr* pts[4] = {u, v, u + sg, v + sg};
+    const Fr* scl[4] = {&S->alpha, &S->beta, nullptr, nullptr};
+    Fr* outs[4] = {w.aU, w.bV, w.Cu, w.Cv};
+    pg.eq(4, bits, pts, scl, outs);
+  }
   // Phase 1: tables (and, for big tables, round 1 in the same pass), then the rounds.
-  Tabs<3> ta;
-  ta.src[0] = W; ta.src[1] = w.G; ta.src[2] = w.H;
-  ta.dst[0] = w.Wf; ta.dst[1] = w.G; ta.dst[2] = w.H;
+  const Fr* ta_src[3] = {W, w.G, w.H};
+  Fr* ta_dst[3] = {w.Wf, w.G, w.H};
   const uint32_t off_vx = 24 * s1, off_p2 = off_vx + 8, off_vy = off_p2 + 24 * s1;
   if (s1 > tun.tail_log) {
-    launch_phase1_init_round(W, w.G, w.H, c.wiring[i], w.aU, w.bV, w.Cu, w.Cv, n, 1ull << (s1 - 1),
-                             1ull << c.s(i), S, w.partials, rx, proof, tun.max_round_blocks, s);
-    run_phase<FormA>(ta, s1, S, w.partials, rx, proof, &S->vx, proof + off_vx, tun, s, 1);
+    pg.p1_init_round(W, w.G, w.H, c.wiring[i], w.aU, w.bV, w.Cu, w.Cv, n, 1ull << (s1 - 1), 1ull << c.s(i), S,
+                     w.partials, rx, proof, tun);
+    emit_phase<3>(pg, ta_src, ta_dst, s1, S, w.partials, rx, proof, &S->vx, proof + off_vx, tun, 1);
   } else {
-    launch_phase1_init(W, w.G, w.H, c.wiring[i], w.aU, w.bV, w.Cu, w.Cv, n, 1ull << s1,
-                       1ull << c.s(i), s);
-    run_phase<FormA>(ta, s1, S, w.partials, rx, proof, &S->vx, proof + off_vx, tun, s);
+    pg.p1_init(W, w.G, w.H, c.wiring[i], w.aU, w.bV, w.Cu, w.Cv, n, 1ull << s1, 1ull << c.s(i));
+    emit_phase<3>(pg, ta_src, ta_dst, s1, S, w.partials, rx, proof, &S->vx, proof + off_vx, tun);
   }
-
   // Phase 2: sub-circuit rounds with the copy factors contracted, then the copy rounds.
-  EqJobs e2{};
-  e2.count = 2;
-  e2.bits[0] = sg1; e2.point[0] = rx; e2.scale[0] = nullptr; e2.out[0] = w.EL;
-  e2.bits[1] = n; e2.point[1] = rx + sg1; e2.scale[1] = nullptr; e2.out[1] = w.EC;
-  launch_eq_tables(e2, s);
-  launch_copy_weights(w.Cu, w.Cv, w.EC, w.U, w.V, 1ull << n, S, s);
-  launch_phase2_tables(c.wiring[i], w.aU, w.bV, w.EL, S, w.Fa, w.Fb, w.Ka, w.Kb, w.Ks, 1ull << sg1,
-                       1ull << sg, s);
-  launch_copy_contract(W, w.U, w.V, w.P, w.Q, n, 1ull << sg1, s);
-  Tabs<5> tb;
-  tb.src[0] = w.P; tb.src[1] = w.Fa; tb.src[2] = w.Q; tb.src[3] = w.Fb; tb.src[4] = w.Ks;
-  for (int k = 0; k < 5; ++k) tb.dst[k] = const_cast<Fr*>(tb.src[k]);
-  run_phase<FormB>(tb, sg1, S, w.partials, ry, proof + off_p2, &S->scratch[1], nullptr, tun, s);
-
-  EqJobs e3{};
-  e3.count = 1;
-  e3.bits[0] = sg1; e3.point[0] = ry; e3.scale[0] = nullptr; e3.out[0] = w.EqR;
-  launch_eq_tables(e3, s);
-  launch_local_values(w.EqR, w.Ka, w.Kb, 1ull << sg1, S, s);
-  launch_local_contract(W, w.EqR, w.wpart, n, 1ull << sg1, c.plan.ychunks, s);
-  launch_copy_tables(w.wpart, c.plan.ychunks, w.U, w.V, w.Fa, w.Fb, S, w.Wc, w.Fc, w.Kc, 1ull << n, s);
-  Tabs<3> tc;
-  tc.src[0] = w.Wc; tc.src[1] = w.Fc; tc.src[2] = w.Kc;
-  tc.dst[0] = w.Wc; tc.dst[1] = w.Fc; tc.dst[2] = w.Kc;
-  run_phase<FormA>(tc, n, S, w.partials, ry + sg1, proof + off_p2 + 24 * sg1, &S->vy,
-                   proof + off_vy, tun, s);
+  {
+    const uint32_t bits[2] = {sg1, n};
+    const Fr* pts[2] = {rx, rx + sg1};
+    const Fr* scl[2] = {nullptr, nullptr};
+    Fr* outs[2] = {w.EL, w.EC};
+    pg.eq(2, bits, pts, scl, outs);
+  }
+  pg.copy_weights(w.Cu, w.Cv, w.EC, w.U, w.V, 1ull << n, S);
+  pg.p2_tables(c.wiring[i], w.aU, w.bV, w.EL, S, w.Fa, w.Fb, w.Ka, w.Kb, w.Ks, 1ull << sg1, 1ull << sg);
+  pg.copy_contract(W, w.U, w.V, w.P, w.Q, n, 1ull << sg1);
+  Fr* tb[5] = {w.P, w.Fa, w.Q, w.Fb, w.Ks};
+  const Fr* tb_src[5] = {w.P, w.Fa, w.Q, w.Fb, w.Ks};
+  emit_phase<5>(pg, tb_src, tb, sg1, S, w.partials, ry, proof + off_p2, &S->scratch[1], nullptr, tun);
+  {
+    const uint32_t bits[1] = {sg1};
+    const Fr* pts[1] = {ry};
+    const Fr* scl[1] = {nullptr};
+    Fr* outs[1] = {w.EqR};
+    pg.eq(1, bits, pts, scl, outs);
+  }
+  pg.local_values(w.EqR, w.Ka, w.Kb, 1ull << sg1, S);
+  pg.local_contract(W, w.EqR, w.wpart, n, 1ull << sg1, c.plan.ychunks);
+  pg.copy_tables(w.wpart, c.plan.ychunks, w.U, w.V, w.Fa, w.Fb, S, w.Wc, w.Fc, w.Kc, 1ull << n);
+  Fr* tc[3] = {w.Wc, w.Fc, w.Kc};
+  const Fr* tc_src[3] = {w.Wc, w.Fc, w.Kc};
+  emit_phase<3>(pg, tc_src, tc, n, S, w.partials, ry + sg1, proof + off_p2 + 24 * sg1, &S->vy, proof + off_vy, tun);
 }
 
 // Forward evaluation of every layer from Montgomery inputs in layer[d].
-static void run_forward(const gkr_circuit& c, const Workspace& w, hipStream_t s) {
+static void emit_forward(Program& pg, const gkr_circuit& c, const Workspace& w) {
   for (int i = (int)c.depth - 1; i >= 0; --i)
-    launch_forward(w.layer[i + 1], w.layer[i], c.wiring[i].gates, c.n, 1ull << c.s(i),
-                   (uint64_t)c.mul_gates[i] << c.n, s);
+    pg.forward(w.layer[i + 1], w.layer[i], c.wiring[i].gates, c.n, 1ull << c.s(i), (uint64_t)c.mul_gates[i] << c.n);
 }
 
 // g and the output claim V_0~(g) (into S->scratch[0]); needs layer[0] in Montgomery form.
-static void run_output_claim(const gkr_circuit& c, const Workspace& w, hipStream_t s) {
+static void emit_output_claim(Program& pg, const gkr_circuit& c, const Workspace& w, const Tuning& tun) {
   DevState* S = w.state;
   Fr* g = w.chal;
-  launch_squeeze(S, g, c.s(0), s);
-  EqJobs e{};
-  e.count = 2;
-  e.bits[0] = c.sigma[0]; e.point[0] = g; e.scale[0] = nullptr; e.out[0] = w.aU;
-  e.bits[1] = c.n; e.point[1] = g + c.sigma[0]; e.scale[1] = nullptr; e.out[1] = w.Cu;
-  launch_eq_tables(e, s);
-  launch_weighted_sum(w.layer[0], w.aU, w.Cu, c.n, 1ull << c.s(0), w.partials, &S->counter,
-                      &S->scratch[0], current_tuning().max_round_blocks, s);
+  pg.squeeze(S, g, c.s(0));
+  const uint32_t bits[2] = {c.sigma[0], c.n};
+  const Fr* pts[2] = {g, g + c.sigma[0]};
+  const Fr* scl[2] = {nullptr, nullptr};
+  Fr* outs[2] = {w.aU, w.Cu};
+  pg.eq(2, bits, pts, scl, outs);
+  pg.wsum(w.layer[0], w.aU, w.Cu, c.n, 1ull << c.s(0), w.partials, S, &S->scratch[0], tun);
 }
 
 static size_t layer_proof_words(const gkr_circuit& c, uint32_t i) { return (6ull * c.s(i + 1) + 2) * 8; }
+
+// The whole proof of gkr_prove_circuit as a step program.
+void emit_prove_circuit(Program& pg, const gkr_circuit& c, const Workspace& w, const gkr_fr* d_inputs,
+                        uint64_t seed, gkr_fr* d_outputs, uint8_t* d_proof, const Tuning& tun) {
+  pg.to_mont(d_inputs, w.layer[c.depth], 1ull << c.s(c.depth));
+  emit_forward(pg, c, w);
+  pg.from_mont(w.layer[0], d_outputs, 1ull << c.s(0));
+  pg.digest(d_inputs, 1ull << c.s(c.depth), w.dig_in, w);
+  pg.digest(d_outputs, 1ull << c.s(0), w.dig_out, w);
+  pg.transcript_begin(w.state, seed_state(seed), c.digest, w.dig_in, w.dig_out);
+  emit_output_claim(pg, c, w, tun);
+  uint32_t* proof = reinterpret_cast<uint32_t*>(d_proof);
+  DevState* S = w.state;
+  for (uint32_t i = 0; i < c.depth; ++i) {
+    const Fr* u = (i == 0) ? w.chal : w.chal + host_chal_index_rx(c, i - 1);
+    const Fr* v = (i == 0) ? w.chal : w.chal + host_chal_index_ry(c, i - 1);
+    const Fr* vu = (i == 0) ? &S->scratch[0] : &S->vx;
+    emit_layer(pg, c, i, w, w.layer[i + 1], u, v, vu, &S->vy, w.chal + host_chal_index_rx(c, i),
+               w.chal + host_chal_index_ry(c, i), proof, tun);
+    proof += layer_proof_words(c, i);
+  }
+}
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
@@ -306,7 +535,7 @@ static int32_t check_launch() {
   return GKR_OK;
 }
 
-static int32_t check_ws(const gkr_circuit* c, void* ws, size_t ws_bytes) {
+int32_t check_ws(const gkr_circuit* c, const void* ws, size_t ws_bytes) {
   if (c->device < 0) {
     set_error("circuit was created without a HIP device (host-only: verification only)");
     return GKR_EDEVICE;
@@ -520,14 +749,18 @@ int32_t gkr_transcript_init(const gkr_circuit* c, uint64_t seed, const gkr_fr* d
   }
   int32_t rc = check_ws(c, d_ws, ws_bytes);
   if (rc) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  Workspace w = bind_workspace(*c, d_ws);
-  Words8 circ;
-  memcpy(circ.w, c->digest, 32);
-  run_digest(d_inputs, 1ull << c->s(c->depth), w.dig_in, w, s);
-  run_digest(d_outputs, 1ull << c->s(0), w.dig_out, w, s);
-  launch_transcript_begin(w.state, seed_state(seed), circ, w.dig_in, w.dig_out, s);
-  launch_state_export(w.state, d_state, s);
+  try {
+    Workspace w = bind_workspace(*c, d_ws);
+    Program pg;
+    pg.digest(d_inputs, 1ull << c->s(c->depth), w.dig_in, w);
+    pg.digest(d_outputs, 1ull << c->s(0), w.dig_out, w);
+    pg.transcript_begin(w.state, seed_state(seed), c->digest, w.dig_in, w.dig_out);
+    pg.state_export(w.state, d_state);
+    pg.run(static_cast<hipStream_t>(stream));
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return GKR_ENOMEM;
+  }
   return check_launch();
 }
 
@@ -540,14 +773,20 @@ int32_t gkr_output_claim(const gkr_circuit* c, const gkr_fr* d_outputs, uint8_t*
   }
   int32_t rc = check_ws(c, d_ws, ws_bytes);
   if (rc) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  Workspace w = bind_workspace(*c, d_ws);
-  launch_state_import(w.state, d_state, s);
-  launch_to_mont(d_outputs, w.layer[0], 1ull << c->s(0), s);
-  run_output_claim(*c, w, s);
-  if (c->s(0) > 0) launch_from_mont(w.chal, d_g, c->s(0), s);
-  launch_from_mont(&w.state->scratch[0], d_claim, 1, s);
-  launch_state_export(w.state, d_state, s);
+  try {
+    Workspace w = bind_workspace(*c, d_ws);
+    Program pg;
+    pg.state_import(w.state, d_state);
+    pg.to_mont(d_outputs, w.layer[0], 1ull << c->s(0));
+    emit_output_claim(pg, *c, w, current_tuning());
+    if (c->s(0) > 0) pg.from_mont(w.chal, d_g, c->s(0));
+    pg.from_mont(&w.state->scratch[0], d_claim, 1);
+    pg.state_export(w.state, d_state);
+    pg.run(static_cast<hipStream_t>(stream));
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return GKR_ENOMEM;
+  }
   return check_launch();
 }
 
@@ -576,32 +815,38 @@ int32_t gkr_prove_layer(const gkr_circuit* c, uint32_t layer, const gkr_fr* d_ne
     }
   int32_t rc = check_ws(c, d_ws, ws_bytes);
   if (rc) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  Workspace w = bind_workspace(*c, d_ws);
-  const uint32_t sc = chal_index_scratch(*c);
-  const uint32_t smax = s_max_of(*c);
-  Fr* u = w.chal + sc;
-  Fr* v = u + smax;
-  Fr* cl = v + smax;  // cl[0] = claim_u, cl[1] = claim_v
-  launch_state_import(w.state, d_state, s);
-  launch_to_mont(d_next, w.layer[layer + 1], 1ull << s1, s);
-  if (si > 0) {
-    launch_to_mont(d_u, u, si, s);
-    launch_to_mont(first ? d_u : d_v, v, si, s);
+  try {
+    Workspace w = bind_workspace(*c, d_ws);
+    const uint32_t sc = chal_index_scratch(*c);
+    const uint32_t smax = s_max_of(*c);
+    Fr* u = w.chal + sc;
+    Fr* v = u + smax;
+    Fr* cl = v + smax;  // cl[0] = claim_u, cl[1] = claim_v
+    Program pg;
+    pg.state_import(w.state, d_state);
+    pg.to_mont(d_next, w.layer[layer + 1], 1ull << s1);
+    if (si > 0) {
+      pg.to_mont(d_u, u, si);
+      pg.to_mont(first ? d_u : d_v, v, si);
+    }
+    pg.to_mont(d_claim_u, cl, 1);
+    pg.to_mont(first ? d_claim_u : d_claim_v, cl + 1, 1);
+    Fr* rx = w.chal + host_chal_index_rx(*c, layer);
+    Fr* ry = w.chal + host_chal_index_ry(*c, layer);
+    emit_layer(pg, *c, layer, w, w.layer[layer + 1], u, v, cl, cl + 1, rx, ry,
+               reinterpret_cast<uint32_t*>(d_layer_proof), current_tuning());
+    if (s1 > 0) {
+      pg.from_mont(rx, d_rx, s1);
+      pg.from_mont(ry, d_ry, s1);
+    }
+    pg.from_mont(&w.state->vx, d_vx, 1);
+    pg.from_mont(&w.state->vy, d_vy, 1);
+    pg.state_export(w.state, d_state);
+    pg.run(static_cast<hipStream_t>(stream));
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return GKR_ENOMEM;
   }
-  launch_to_mont(d_claim_u, cl, 1, s);
-  launch_to_mont(first ? d_claim_u : d_claim_v, cl + 1, 1, s);
-  Fr* rx = w.chal + host_chal_index_rx(*c, layer);
-  Fr* ry = w.chal + host_chal_index_ry(*c, layer);
-  run_layer(*c, layer, w, w.layer[layer + 1], u, v, cl, cl + 1, rx, ry,
-            reinterpret_cast<uint32_t*>(d_layer_proof), current_tuning(), s);
-  if (s1 > 0) {
-    launch_from_mont(rx, d_rx, s1, s);
-    launch_from_mont(ry, d_ry, s1, s);
-  }
-  launch_from_mont(&w.state->vx, d_vx, 1, s);
-  launch_from_mont(&w.state->vy, d_vy, 1, s);
-  launch_state_export(w.state, d_state, s);
   return check_launch();
 }
 
@@ -621,27 +866,14 @@ int32_t gkr_prove_circuit(const gkr_circuit* c, const gkr_fr* d_inputs, uint64_t
   }
   int32_t rc = check_ws(c, d_ws, ws_bytes);
   if (rc) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  Workspace w = bind_workspace(*c, d_ws);
-  const Tuning tun = current_tuning();
-  launch_to_mont(d_inputs, w.layer[c->depth], 1ull << c->s(c->depth), s);
-  run_forward(*c, w, s);
-  launch_from_mont(w.layer[0], d_outputs, 1ull << c->s(0), s);
-  Words8 circ;
-  memcpy(circ.w, c->digest, 32);
-  run_digest(d_inputs, 1ull << c->s(c->depth), w.dig_in, w, s);
-  run_digest(d_outputs, 1ull << c->s(0), w.dig_out, w, s);
-  launch_transcript_begin(w.state, seed_state(seed), circ, w.dig_in, w.dig_out, s);
-  run_output_claim(*c, w, s);
-  uint32_t* proof = reinterpret_cast<uint32_t*>(d_proof);
-  DevState* S = w.state;
-  for (uint32_t i = 0; i < c->depth; ++i) {
-    const Fr* u = (i == 0) ? w.chal : w.chal + host_chal_index_rx(*c, i - 1);
-    const Fr* v = (i == 0) ? w.chal : w.chal + host_chal_index_ry(*c, i - 1);
-    const Fr* vu = (i == 0) ? &S->scratch[0] : &S->vx;
-    run_layer(*c, i, w, w.layer[i + 1], u, v, vu, &S->vy, w.chal + host_chal_index_rx(*c, i),
-              w.chal + host_chal_index_ry(*c, i), proof, tun, s);
-    proof += layer_proof_words(*c, i);
+  try {
+    Workspace w = bind_workspace(*c, d_ws);
+    Program pg;
+    emit_prove_circuit(pg, *c, w, d_inputs, seed, d_outputs, d_proof, current_tuning());
+    pg.run(static_cast<hipStream_t>(stream));
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return GKR_ENOMEM;
   }
   return check_launch();
 }

@@ -1,0 +1,125 @@
+// Device helpers of the GKR kernels: element loads/stores, wave shuffles,
+// workgroup reductions and the last-tile protocol of grid-wide reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gkr_internal.hpp"
+#include "gkr_kernels.hpp"
+
+namespace gkr {
+
+__device__ __forceinline__ Fr ldf(const Fr* p, uint64_t i) {
+  const uint4* q = reinterpret_cast<const uint4*>(p + i);
+  uint4 a = q[0], b = q[1];
+  return fr_make(a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w);
+}
+
+__device__ __forceinline__ void stf(Fr* p, uint64_t i, const Fr& v) {
+  uint4* q = reinterpret_cast<uint4*>(p + i);
+  q[0] = make_uint4(v.v[0], v.v[1], v.v[2], v.v[3]);
+  q[1] = make_uint4(v.v[4], v.v[5], v.v[6], v.v[7]);
+}
+
+__device__ __forceinline__ Fr shfl_xor_fr(const Fr& a, int mask) {
+  Fr r;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) r.v[k] = (uint32_t)__shfl_xor((int)a.v[k], mask, 64);
+  return r;
+}
+
+// The value of lane `src` in every lane of the wave.
+__device__ __forceinline__ Fr shfl_fr(const Fr& a, int src) {
+  Fr r;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) r.v[k] = (uint32_t)__shfl((int)a.v[k], src, 64);
+  return r;
+}
+
+template <class T>
+__device__ __forceinline__ T P(const Step& st, int i) {
+  return reinterpret_cast<T>(const_cast<void*>(st.p[i]));
+}
+
+// Sum of NV values over the workgroup; the totals are valid in thread 0.
+template <int NV>
+__device__ void block_reduce(Fr (&v)[NV]) {
+  __shared__ Fr red[NV][kBlock / 64];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = fr_add(v[k], shfl_xor_fr(v[k], off));
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k][wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      Fr acc = red[k][0];
+#pragma unroll
+      for (int w = 1; w < kBlock / 64; ++w) acc = fr_add(acc, red[k][w]);
+      v[k] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+// Copies thread 0's values to every thread of the workgroup.
+template <int NV>
+__device__ void broadcast_from_thread0(Fr (&v)[NV]) {
+  __shared__ Fr bc[NV];
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) bc[k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = bc[k];
+  __syncthreads();
+}
+
+// Workgroup sum of NV values, stored as the tile's partials.
+template <int NV>
+__device__ void write_partial(Fr (&v)[NV], Fr* partials, uint32_t tile) {
+  block_reduce<NV>(v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) stf(partials, (uint64_t)tile * NV + k, v[k]);
+  }
+}
+
+// Publishes this tile's writes and counts it; true (in every thread) for the
+// last of ntiles tiles, which then sees all tiles' writes. The counter is back
+// at zero afterwards.
+__device__ __forceinline__ bool last_tile(uint32_t* counter, uint32_t ntiles) {
+  __shared__ int is_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t prev = atomicAdd(counter, 1u);
+    is_last = (prev == ntiles - 1);
+    if (is_last) atomicExch(counter, 0u);
+  }
+  __syncthreads();
+  const bool last = is_last;
+  if (last) __threadfence();
+  return last;
+}
+
+// Sum of the partials of ntiles tiles; the totals are valid in thread 0.
+template <int NV>
+__device__ void sum_partials(const Fr* partials, uint32_t ntiles, Fr (&out)[NV]) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) out[k] = fr_zero();
+  for (uint32_t b = threadIdx.x; b < ntiles; b += kBlock) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] = fr_add(out[k], ldf(partials, (uint64_t)b * NV + k));
+  }
+  block_reduce<NV>(out);
+}
+
+}  // namespace gkr

@@ -6,111 +6,34 @@
 // of a table sweep is coalesced. Gate g = z*2^n + c keeps the copy index in the
 // low bits: a gather W[(y_z << n) | c] over consecutive c is contiguous.
 //
+// Each kernel is a step body over (tile, ntiles): tile plays the role of the
+// workgroup index and ntiles of the grid size. The plain path launches one
+// kernel per step with grid = ntiles; the persistent batch kernel
+// (gkr_batch.hip) hands tiles of many proofs' steps to resident workgroups.
+//
 // Reductions over a whole table (the round polynomials of the sumcheck) end in
-// the last workgroup to finish: each workgroup writes its partial sums,
-// publishes them with a device-scope fence and an atomic counter, and the
-// workgroup that brings the counter to the grid size adds the partials and runs
-// the Fiat-Shamir step (absorb the message, squeeze the next challenge, move the
-// claim) on one thread. Challenges and claims never leave device memory, so a
-// proof is a plain sequence of launches on one stream.
+// the last tile to finish: each tile writes its partial sums, publishes them
+// with a device-scope fence and an atomic counter, and the tile that brings the
+// counter to ntiles adds the partials and runs the Fiat-Shamir step (absorb
+// the message, take the challenge, move the claim) in its first wave.
+// Challenges and claims never leave device memory, so a proof is a plain
+// sequence of launches on one stream.
+#include "gkr_device.hpp"
 #include "gkr_kernels.hpp"
 #include "gkr_profile.hpp"
 
 namespace gkr {
 
-// ----------------------------------------------------------------- helpers
-
-__device__ __forceinline__ Fr ldf(const Fr* p, uint64_t i) {
-  const uint4* q = reinterpret_cast<const uint4*>(p + i);
-  uint4 a = q[0], b = q[1];
-  return fr_make(a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w);
-}
-
-__device__ __forceinline__ void stf(Fr* p, uint64_t i, const Fr& v) {
-  uint4* q = reinterpret_cast<uint4*>(p + i);
-  q[0] = make_uint4(v.v[0], v.v[1], v.v[2], v.v[3]);
-  q[1] = make_uint4(v.v[4], v.v[5], v.v[6], v.v[7]);
-}
-
-__device__ __forceinline__ Fr shfl_xor_fr(const Fr& a, int mask) {
-  Fr r;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) r.v[k] = (uint32_t)__shfl_xor((int)a.v[k], mask, 64);
-  return r;
-}
-
-__device__ __forceinline__ uint64_t gtid() { return (uint64_t)blockIdx.x * kBlock + threadIdx.x; }
-__device__ __forceinline__ uint64_t gstride() { return (uint64_t)gridDim.x * kBlock; }
-
-// Sum of NV values over the workgroup; the totals are valid in thread 0.
-template <int NV>
-__device__ void block_reduce(Fr (&v)[NV]) {
-  __shared__ Fr red[NV][kBlock / 64];
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = fr_add(v[k], shfl_xor_fr(v[k], off));
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) red[k][wid] = v[k];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      Fr acc = red[k][0];
-#pragma unroll
-      for (int w = 1; w < kBlock / 64; ++w) acc = fr_add(acc, red[k][w]);
-      v[k] = acc;
-    }
-  }
-  __syncthreads();
-}
-
-// Grid-wide sum. Returns true in the last workgroup to finish, where thread 0
-// then holds the totals; the counter is back at zero afterwards.
-template <int NV>
-__device__ bool grid_reduce(Fr (&v)[NV], Fr* partials, uint32_t* counter) {
-  block_reduce<NV>(v);
-  __shared__ int is_last;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) stf(partials, (uint64_t)blockIdx.x * NV + k, v[k]);
-    __threadfence();
-    uint32_t prev = atomicAdd(counter, 1u);
-    is_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-  Fr acc[NV];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) acc[k] = fr_zero();
-  for (uint32_t b = threadIdx.x; b < gridDim.x; b += kBlock) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = fr_add(acc[k], ldf(partials, (uint64_t)b * NV + k));
-  }
-  block_reduce<NV>(acc);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = acc[k];
-    atomicExch(counter, 0u);
-  }
-  return true;
-}
-
 // ---------------------------------------------------------- transcript
 
-// SHA-256 of a fixed-length word message (big-endian words), fully unrolled.
+// SHA-256 of a fixed-length word message (big-endian words).
 template <int L>
-__device__ Sha256State sha256_fixed(const uint32_t* w) {
+__device__ __forceinline__ Sha256State sha256_fixed(const uint32_t* w) {
   constexpr int B = (L + 3 + 15) / 16;
   Sha256State st = sha256_iv();
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    uint32_t blk[16];
+    Sha256Block blk;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int idx = b * 16 + i;
@@ -119,37 +42,23 @@ __device__ Sha256State sha256_fixed(const uint32_t* w) {
       else if (idx == L) v = 0x80000000u;
       else if (idx == B * 16 - 1) v = (uint32_t)(L * 32);
       else v = 0u;
-      blk[i] = v;
+      blk.w[i] = v;
     }
-    sha256_compress(st, blk);
+    st = sha256_compress_v(st, blk);
   }
   return st;
 }
 
-__device__ Sha256State load_state(const DevState* S) {
+__device__ __forceinline__ Sha256State load_state(const DevState* S) {
   Sha256State s;
 #pragma unroll
   for (int k = 0; k < 8; ++k) s.h[k] = S->st[k];
   return s;
 }
 
-__device__ void save_state(DevState* S, const Sha256State& s) {
+__device__ __forceinline__ void save_state(DevState* S, const Sha256State& s) {
 #pragma unroll
   for (int k = 0; k < 8; ++k) S->st[k] = s.h[k];
-}
-
-// Field products of the serial Fiat-Shamir code: one out-of-line copy keeps
-// the single-thread paths small.
-__device__ __attribute__((noinline)) Fr fr_mul_ni(Fr a, Fr b) { return fr_mul(a, b); }
-__device__ __forceinline__ Fr to_mont_ni(const Fr& a) { return fr_mul_ni(a, fr_r2()); }
-__device__ __forceinline__ Fr from_mont_ni(const Fr& a) { return fr_mul_ni(a, fr_make(1, 0, 0, 0, 0, 0, 0, 0)); }
-
-// g(r) for the degree-2 polynomial with values e0, e1, e2 at t = 0, 1, 2.
-__device__ Fr interp3_ni(const Fr& e0, const Fr& e1, const Fr& e2, const Fr& r) {
-  const Fr d1 = fr_sub(e1, e0);
-  const Fr d2 = fr_add(fr_sub(e2, fr_double(e1)), e0);
-  const Fr rr = fr_mul_ni(fr_mul_ni(r, fr_sub(r, fr_one())), fr_inv2());
-  return fr_add(fr_add(e0, fr_mul_ni(r, d1)), fr_mul_ni(rr, d2));
 }
 
 // The current state as a challenge: rehash with "GKRC" until the 254-bit
@@ -197,11 +106,25 @@ __device__ void absorb_digest(Sha256State& st, const uint32_t* d) {
   st = sha256_fixed<17>(w);
 }
 
-// Round message (e0, e1 = claim - e0, e2): write it to the proof, absorb
-// (e0, e2), take the challenge r from the state, store r and move the claim to g(r).
-__device__ void finish_round(DevState* S, const Fr& e0, const Fr& e2, Fr* r_out,
-                             uint32_t* msg_out) {
-  const Fr c0 = from_mont_ni(e0), c2 = from_mont_ni(e2);
+__device__ __forceinline__ Fr fr_one_canonical() { return fr_make(1, 0, 0, 0, 0, 0, 0, 0); }
+
+// Round message (e0, e1 = claim - e0, e2), run by all 64 lanes of one wave
+// with e0, e2 the same in every lane: write the message to the proof, absorb
+// (e0, e2), take the challenge r, store r and move the claim to
+// g(r) = e0 + r (e1 - e0) + r (r - 1) (e2 - 2 e1 + e0) / 2.
+// Independent products run in different lanes: 4 products on the serial path.
+__device__ void finish_round_wave(DevState* S, const Fr& e0, const Fr& e2, Fr* r_out,
+                                  uint32_t* msg_out) {
+  const int lane = threadIdx.x & 63;
+  const Fr claim = S->claim;
+  const Fr e1 = fr_sub(claim, e0);
+  const Fr d1 = fr_sub(e1, e0);
+  const Fr d2 = fr_add(fr_sub(e2, fr_double(e1)), e0);
+  // lanes 0, 1, 2: canonical e0, canonical e2, d2 / 2
+  Fr a = lane == 0 ? e0 : (lane == 1 ? e2 : d2);
+  Fr b = lane < 2 ? fr_one_canonical() : fr_inv2();
+  Fr prod = fr_mul(a, b);
+  const Fr c0 = shfl_fr(prod, 0), c2 = shfl_fr(prod, 1), d2h = shfl_fr(prod, 2);
   uint32_t w[25];
   Sha256State st = load_state(S);
 #pragma unroll
@@ -213,23 +136,31 @@ __device__ void finish_round(DevState* S, const Fr& e0, const Fr& e2, Fr* r_out,
     w[17 + k] = bswap32(c2.v[k]);
   }
   st = sha256_fixed<25>(w);
-  const Fr r = to_mont_ni(accept(st));
-  stf(r_out, 0, r);
-  save_state(S, st);
-  const Fr e1 = fr_sub(S->claim, e0);
-  const Fr c1 = from_mont_ni(e1);
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    msg_out[k] = c0.v[k];
-    msg_out[8 + k] = c1.v[k];
-    msg_out[16 + k] = c2.v[k];
+  const Fr r = fr_mul(accept(st), fr_r2());
+  if (lane == 0) {
+    stf(r_out, 0, r);
+    save_state(S, st);
   }
-  S->claim = interp3_ni(e0, e1, e2, r);
+  // lanes 0, 1, 2: r d1, r (r - 1), canonical e1
+  a = lane == 2 ? e1 : r;
+  b = lane == 0 ? d1 : (lane == 1 ? fr_sub(r, fr_one()) : fr_one_canonical());
+  prod = fr_mul(a, b);
+  const Fr rd1 = shfl_fr(prod, 0), rr = shfl_fr(prod, 1), c1 = shfl_fr(prod, 2);
+  const Fr quad = fr_mul(rr, d2h);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      msg_out[k] = c0.v[k];
+      msg_out[8 + k] = c1.v[k];
+      msg_out[16 + k] = c2.v[k];
+    }
+    S->claim = fr_add(fr_add(e0, rd1), quad);
+  }
 }
 
-// A phase's final value: store it, write it to the proof and absorb it.
+// A phase's final value (one thread): store it, write it to the proof and absorb it.
 __device__ void finish_value(DevState* S, const Fr& v, Fr* v_out, uint32_t* proof_out) {
-  const Fr c = from_mont_ni(v);
+  const Fr c = fr_from_mont(v);
   Sha256State st = load_state(S);
   absorb_element(st, kTagValue, c);
   save_state(S, st);
@@ -238,26 +169,34 @@ __device__ void finish_value(DevState* S, const Fr& v, Fr* v_out, uint32_t* proo
   for (int k = 0; k < 8; ++k) proof_out[k] = c.v[k];
 }
 
-// ------------------------------------------------------------- kernels
+// ---------------------------------------------------------------- bodies
 
-__global__ void __launch_bounds__(kBlock) k_to_mont(const gkr_fr* in, Fr* out, uint64_t n) {
-  for (uint64_t i = gtid(); i < n; i += gstride()) {
-    Fr a = ldf(reinterpret_cast<const Fr*>(in), i);
-    stf(out, i, fr_to_mont(a));
-  }
+#define GTID ((uint64_t)tile * kBlock + threadIdx.x)
+#define GSTRIDE ((uint64_t)ntiles * kBlock)
+
+// ST_TO_MONT: p0 canonical in, p1 out, q0 count.
+__device__ void body_to_mont(const Step& st, uint32_t tile, uint32_t ntiles) {
+  const Fr* in = P<const Fr*>(st, 0);
+  Fr* out = P<Fr*>(st, 1);
+  for (uint64_t i = GTID; i < st.q[0]; i += GSTRIDE) stf(out, i, fr_to_mont(ldf(in, i)));
 }
 
-__global__ void __launch_bounds__(kBlock) k_from_mont(const Fr* in, gkr_fr* out, uint64_t n) {
-  for (uint64_t i = gtid(); i < n; i += gstride())
-    stf(reinterpret_cast<Fr*>(out), i, fr_from_mont(ldf(in, i)));
+// ST_FROM_MONT: p0 in, p1 canonical out, q0 count.
+__device__ void body_from_mont(const Step& st, uint32_t tile, uint32_t ntiles) {
+  const Fr* in = P<const Fr*>(st, 0);
+  Fr* out = P<Fr*>(st, 1);
+  for (uint64_t i = GTID; i < st.q[0]; i += GSTRIDE) stf(out, i, fr_from_mont(ldf(in, i)));
 }
 
-// V_i[z*2^n + c] = W[x_z*2^n + c] (+ or *) W[y_z*2^n + c].
-__global__ void __launch_bounds__(kBlock)
-    k_forward(const Fr* __restrict__ W, Fr* __restrict__ V, const uint2* __restrict__ gates,
-              uint32_t n, uint64_t count) {
+// ST_FORWARD: V_i[z*2^n + c] = W[x_z*2^n + c] (+ or *) W[y_z*2^n + c].
+// p0 W, p1 V, p2 gate records, u0 n, q0 count.
+__device__ void body_forward(const Step& st, uint32_t tile, uint32_t ntiles) {
+  const Fr* __restrict__ W = P<const Fr*>(st, 0);
+  Fr* __restrict__ V = P<Fr*>(st, 1);
+  const uint2* __restrict__ gates = P<const uint2*>(st, 2);
+  const uint32_t n = st.u[0];
   const uint64_t mask = (1ull << n) - 1;
-  for (uint64_t g = gtid(); g < count; g += gstride()) {
+  for (uint64_t g = GTID; g < st.q[0]; g += GSTRIDE) {
     const uint64_t z = g >> n, c = g & mask;
     const uint2 gate = gates[z];
     const uint64_t x = gate.x & 0x7fffffffu, y = gate.y;
@@ -266,141 +205,165 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// One level of a tree digest: chunk t of `nwords` words (2048 per chunk) is
-// hashed by thread t; element words are byte-swapped (limbs are little-endian).
-__global__ void __launch_bounds__(kBlock)
-    k_digest_level(const uint32_t* __restrict__ in, uint64_t nwords, int swap,
-                   uint32_t* __restrict__ out, uint64_t nchunks) {
-  const uint64_t t = gtid();
-  if (t >= nchunks) return;
-  const uint64_t begin = t * kChunkWords;
-  const uint64_t end = (begin + kChunkWords < nwords) ? begin + kChunkWords : nwords;
-  const uint64_t len = end - begin;  // a multiple of 8 words
-  Sha256State st = sha256_iv();
-  const uint4* src = reinterpret_cast<const uint4*>(in + begin);
-  const uint64_t full = len / 16;
-  for (uint64_t b = 0; b < full; ++b) {
-    uint32_t blk[16];
+// ST_DIGEST: one level of a tree digest; chunk t of q0 words (256 words, 1 KiB,
+// per chunk) is hashed by thread t; element words are byte-swapped (limbs are
+// little-endian). p0 in, p1 out, q0 nwords, q1 nchunks, u0 swap.
+__device__ void body_digest(const Step& st, uint32_t tile, uint32_t ntiles) {
+  const uint32_t* __restrict__ in = P<const uint32_t*>(st, 0);
+  uint32_t* __restrict__ out = P<uint32_t*>(st, 1);
+  const uint64_t nwords = st.q[0];
+  const int swap = st.u[0];
+  for (uint64_t t = GTID; t < st.q[1]; t += GSTRIDE) {
+    const uint64_t begin = t * kChunkWords;
+    const uint64_t end = (begin + kChunkWords < nwords) ? begin + kChunkWords : nwords;
+    const uint64_t len = end - begin;  // a multiple of 8 words
+    Sha256State sh = sha256_iv();
+    const uint4* src = reinterpret_cast<const uint4*>(in + begin);
+    const uint64_t full = len / 16;
+    for (uint64_t b = 0; b < full; ++b) {
+      Sha256Block blk;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint4 v = src[b * 4 + q];
-      blk[4 * q + 0] = swap ? bswap32(v.x) : v.x;
-      blk[4 * q + 1] = swap ? bswap32(v.y) : v.y;
-      blk[4 * q + 2] = swap ? bswap32(v.z) : v.z;
-      blk[4 * q + 3] = swap ? bswap32(v.w) : v.w;
+      for (int q = 0; q < 4; ++q) {
+        const uint4 v = src[b * 4 + q];
+        blk.w[4 * q + 0] = swap ? bswap32(v.x) : v.x;
+        blk.w[4 * q + 1] = swap ? bswap32(v.y) : v.y;
+        blk.w[4 * q + 2] = swap ? bswap32(v.z) : v.z;
+        blk.w[4 * q + 3] = swap ? bswap32(v.w) : v.w;
+      }
+      sh = sha256_compress_v(sh, blk);
     }
-    sha256_compress(st, blk);
-  }
-  uint32_t blk[16];
+    Sha256Block blk;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) blk[i] = 0;
-  const uint64_t rem = len - full * 16;  // 0 or 8
-  if (rem == 8) {
+    for (int i = 0; i < 16; ++i) blk.w[i] = 0;
+    if (len - full * 16 == 8) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const uint4 v = src[full * 4 + q];
-      blk[4 * q + 0] = swap ? bswap32(v.x) : v.x;
-      blk[4 * q + 1] = swap ? bswap32(v.y) : v.y;
-      blk[4 * q + 2] = swap ? bswap32(v.z) : v.z;
-      blk[4 * q + 3] = swap ? bswap32(v.w) : v.w;
+      for (int q = 0; q < 2; ++q) {
+        const uint4 v = src[full * 4 + q];
+        blk.w[4 * q + 0] = swap ? bswap32(v.x) : v.x;
+        blk.w[4 * q + 1] = swap ? bswap32(v.y) : v.y;
+        blk.w[4 * q + 2] = swap ? bswap32(v.z) : v.z;
+        blk.w[4 * q + 3] = swap ? bswap32(v.w) : v.w;
+      }
+      blk.w[8] = 0x80000000u;
+    } else {
+      blk.w[0] = 0x80000000u;
     }
-    blk[8] = 0x80000000u;
-  } else {
-    blk[0] = 0x80000000u;
-  }
-  const uint64_t bits = len * 32;
-  blk[14] = (uint32_t)(bits >> 32);
-  blk[15] = (uint32_t)bits;
-  sha256_compress(st, blk);
+    const uint64_t bits = len * 32;
+    blk.w[14] = (uint32_t)(bits >> 32);
+    blk.w[15] = (uint32_t)bits;
+    sh = sha256_compress_v(sh, blk);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) out[t * 8 + k] = st.h[k];
+    for (int k = 0; k < 8; ++k) out[t * 8 + k] = sh.h[k];
+  }
 }
 
-// Statement binding: st = seed state, then absorb the three digests.
-__global__ void k_transcript_begin(DevState* S, Words8 seed_state, Words8 circuit_digest,
-                                   const uint32_t* dig_in, const uint32_t* dig_out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  Sha256State st;
+// ST_TRANSCRIPT_BEGIN: st = seed state (w0..7), then absorb the circuit digest
+// (w8..15) and the two vector digests; also zeroes the reduction counter.
+// p0 S, p1 dig_in, p2 dig_out.
+__device__ void body_transcript_begin(const Step& st, uint32_t, uint32_t) {
+  if (threadIdx.x != 0) return;
+  DevState* S = P<DevState*>(st, 0);
+  Sha256State sh;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) st.h[k] = seed_state.w[k];
-  absorb_digest(st, circuit_digest.w);
-  absorb_digest(st, dig_in);
-  absorb_digest(st, dig_out);
-  save_state(S, st);
+  for (int k = 0; k < 8; ++k) sh.h[k] = st.w[k];
+  absorb_digest(sh, st.w + 8);
+  absorb_digest(sh, P<const uint32_t*>(st, 1));
+  absorb_digest(sh, P<const uint32_t*>(st, 2));
+  save_state(S, sh);
   S->counter = 0;
 }
 
-// Squeeze `count` challenges into out[0..count) (Montgomery form).
-__global__ void k_squeeze(DevState* S, Fr* out, uint32_t count) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  Sha256State st = load_state(S);
-  for (uint32_t k = 0; k < count; ++k) stf(out, k, to_mont_ni(squeeze(st)));
-  save_state(S, st);
+// ST_SQUEEZE: u0 challenges into p1 (Montgomery form). p0 S.
+__device__ void body_squeeze(const Step& st, uint32_t, uint32_t) {
+  if (threadIdx.x != 0) return;
+  DevState* S = P<DevState*>(st, 0);
+  Fr* out = P<Fr*>(st, 1);
+  Sha256State sh = load_state(S);
+  for (uint32_t k = 0; k < st.u[0]; ++k) stf(out, k, fr_to_mont(squeeze(sh)));
+  save_state(S, sh);
 }
 
-// Start of a gate layer: draw alpha, beta (layer > 0) and set the claim to
-// alpha * vu + beta * vv; on layer 0 alpha = 1, beta = 0 and claim = vu.
-__global__ void k_layer_begin(DevState* S, int first, const Fr* vu, const Fr* vv) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (first) {
+// ST_LAYER_BEGIN: draw alpha, beta (layer > 0) and set the claim to
+// alpha * vu + beta * vv; on layer 0 (u0 = 1) alpha = 1, beta = 0 and claim = vu.
+// p0 S, p1 vu, p2 vv.
+__device__ void body_layer_begin(const Step& st, uint32_t, uint32_t) {
+  if (threadIdx.x != 0) return;
+  DevState* S = P<DevState*>(st, 0);
+  const Fr vu = *P<const Fr*>(st, 1), vv = *P<const Fr*>(st, 2);
+  if (st.u[0]) {
     S->alpha = fr_one();
     S->beta = fr_zero();
-    S->claim = *vu;
+    S->claim = vu;
     return;
   }
-  Sha256State st = load_state(S);
-  const Fr a = to_mont_ni(squeeze(st));
-  const Fr b = to_mont_ni(squeeze(st));
-  save_state(S, st);
+  Sha256State sh = load_state(S);
+  const Fr a = fr_to_mont(squeeze(sh));
+  const Fr b = fr_to_mont(squeeze(sh));
+  save_state(S, sh);
   S->alpha = a;
   S->beta = b;
-  S->claim = fr_add(fr_mul_ni(a, *vu), fr_mul_ni(b, *vv));
+  S->claim = fr_add(fr_mul(a, vu), fr_mul(b, vv));
 }
 
-// eq tables: out_j[b] = scale_j * prod_k (bit_k(b) ? r_k : 1 - r_k), bit 1 = MSB.
-__global__ void __launch_bounds__(kBlock) k_eq_tables(EqJobs jobs) {
-  uint64_t t = gtid();
-  for (int j = 0; j < jobs.count; ++j) {
-    const uint64_t size = 1ull << jobs.bits[j];
-    if (t < size) {
-      const Fr* r = jobs.point[j];
-      const int k = jobs.bits[j];
-      Fr acc = jobs.scale[j] ? *jobs.scale[j] : fr_one();
-      for (int i = 0; i < k; ++i) {
-        const Fr ri = ldf(r, i);
-        const bool bit = (t >> (k - 1 - i)) & 1;
-        acc = fr_mul(acc, bit ? ri : fr_one_minus(ri));
-      }
-      stf(jobs.out[j], t, acc);
-      return;
+// ST_EQ: up to four tables out_j[b] = scale_j * prod_k (bit_k(b) ? r_k : 1 - r_k),
+// bit 1 = MSB. u0..3 bits, u4 count; p0..3 points, p4..7 scales (null = 1), p8..11 outs.
+__device__ void body_eq(const Step& st, uint32_t tile, uint32_t ntiles) {
+  uint64_t total = 0;
+  for (uint32_t j = 0; j < st.u[4]; ++j) total += 1ull << st.u[j];
+  for (uint64_t g = GTID; g < total; g += GSTRIDE) {
+    uint64_t t = g;
+    uint32_t j = 0;
+    while (t >= (1ull << st.u[j])) {
+      t -= 1ull << st.u[j];
+      ++j;
     }
-    t -= size;
+    const Fr* r = P<const Fr*>(st, j);
+    const int k = st.u[j];
+    const Fr* scale = P<const Fr*>(st, 4 + j);
+    Fr acc = scale ? *scale : fr_one();
+    for (int i = 0; i < k; ++i) {
+      const Fr ri = ldf(r, i);
+      const bool bit = (t >> (k - 1 - i)) & 1;
+      acc = fr_mul(acc, bit ? ri : fr_one_minus(ri));
+    }
+    stf(P<Fr*>(st, 8 + j), t, acc);
   }
 }
 
-// Weighted sum over a layer: sum_e V[e] A[e >> n] B[e & mask] into *dst.
-__global__ void __launch_bounds__(kBlock)
-    k_weighted_sum(const Fr* __restrict__ V, const Fr* __restrict__ A, const Fr* __restrict__ B,
-                   uint32_t n, uint64_t count, Fr* partials, uint32_t* counter, Fr* dst) {
+// ST_WSUM: sum_e V[e] A[e >> n] B[e & mask] into *p5.
+// p0 V, p1 A, p2 B, p3 partials, p4 S, p5 dst, u0 n, q0 count.
+__device__ void body_wsum(const Step& st, uint32_t tile, uint32_t ntiles) {
+  const Fr* V = P<const Fr*>(st, 0);
+  const Fr* A = P<const Fr*>(st, 1);
+  const Fr* B = P<const Fr*>(st, 2);
+  const uint32_t n = st.u[0];
   const uint64_t mask = (1ull << n) - 1;
   Fr acc[1] = {fr_zero()};
-  for (uint64_t e = gtid(); e < count; e += gstride())
+  for (uint64_t e = GTID; e < st.q[0]; e += GSTRIDE)
     acc[0] = fr_add(acc[0], fr_mul(fr_mul(ldf(V, e), ldf(A, e >> n)), ldf(B, e & mask)));
-  if (grid_reduce<1>(acc, partials, counter) && threadIdx.x == 0) *dst = acc[0];
+  write_partial<1>(acc, P<Fr*>(st, 3), tile);
+}
+__device__ void finish_wsum(const Step& st, uint32_t ntiles) {
+  Fr tot[1];
+  sum_partials<1>(P<const Fr*>(st, 3), ntiles, tot);
+  if (threadIdx.x == 0) *P<Fr*>(st, 5) = tot[0];
 }
 
 // Phase-1 bookkeeping tables over (x, c):
 //   G[x,c] = sum_{MUL z: x_z=x} T[z,c] W[y_z,c] + sum_{ADD z: x_z=x} T[z,c]
 //   H[x,c] = sum_{ADD z: x_z=x} T[z,c] W[y_z,c]
 // with T[z,c] = aU[z] Cu[c] + bV[z] Cv[c] (the factored eq of both claims).
-__device__ __forceinline__ void phase1_entry(const Fr* __restrict__ W, const uint32_t* __restrict__ xrow,
-                                             const uint2* __restrict__ xent, const Fr* __restrict__ aU,
-                                             const Fr* __restrict__ bV, const Fr* __restrict__ Cu,
-                                             const Fr* __restrict__ Cv, uint32_t n, uint64_t e, Fr& g,
-                                             Fr& h) {
+// p0 W, p1 G, p2 H, p3 xrow, p4 xent, p5 aU, p6 bV, p7 Cu, p8 Cv, u0 n.
+__device__ __forceinline__ void phase1_entry(const Step& st, uint64_t e, Fr& g, Fr& h) {
+  const Fr* __restrict__ W = P<const Fr*>(st, 0);
+  const uint32_t* __restrict__ xrow = P<const uint32_t*>(st, 3);
+  const uint2* __restrict__ xent = P<const uint2*>(st, 4);
+  const Fr* __restrict__ aU = P<const Fr*>(st, 5);
+  const Fr* __restrict__ bV = P<const Fr*>(st, 6);
+  const uint32_t n = st.u[0];
   const uint64_t mask = (1ull << n) - 1;
   const uint64_t x = e >> n, c = e & mask;
-  const Fr cu = ldf(Cu, c), cv = ldf(Cv, c);
+  const Fr cu = ldf(P<const Fr*>(st, 7), c), cv = ldf(P<const Fr*>(st, 8), c);
   g = fr_zero();
   h = fr_zero();
   const uint32_t k1 = xrow[x + 1];
@@ -418,34 +381,31 @@ __device__ __forceinline__ void phase1_entry(const Fr* __restrict__ W, const uin
   }
 }
 
-__global__ void __launch_bounds__(kBlock)
-    k_phase1_init(const Fr* __restrict__ W, Fr* __restrict__ G, Fr* __restrict__ H,
-                  const uint32_t* __restrict__ xrow, const uint2* __restrict__ xent,
-                  const Fr* __restrict__ aU, const Fr* __restrict__ bV,
-                  const Fr* __restrict__ Cu, const Fr* __restrict__ Cv, uint32_t n,
-                  uint64_t count) {
-  for (uint64_t e = gtid(); e < count; e += gstride()) {
+// ST_P1_INIT: the tables alone; q0 count.
+__device__ void body_p1_init(const Step& st, uint32_t tile, uint32_t ntiles) {
+  Fr* G = P<Fr*>(st, 1);
+  Fr* H = P<Fr*>(st, 2);
+  for (uint64_t e = GTID; e < st.q[0]; e += GSTRIDE) {
     Fr g, h;
-    phase1_entry(W, xrow, xent, aU, bV, Cu, Cv, n, e, g, h);
+    phase1_entry(st, e, g, h);
     stf(G, e, g);
     stf(H, e, h);
   }
 }
 
-// The tables and the first round together: thread b builds entries b and
-// b + half, evaluates the round-1 pair at t = 0, 2, and the last workgroup
-// runs the Fiat-Shamir step.
-__global__ void __launch_bounds__(kBlock)
-    k_phase1_init_round(const Fr* __restrict__ W, Fr* __restrict__ G, Fr* __restrict__ H,
-                        const uint32_t* __restrict__ xrow, const uint2* __restrict__ xent,
-                        const Fr* __restrict__ aU, const Fr* __restrict__ bV,
-                        const Fr* __restrict__ Cu, const Fr* __restrict__ Cv, uint32_t n,
-                        uint64_t half, DevState* S, Fr* partials, Fr* r_out, uint32_t* msg_out) {
+// ST_P1_INIT_ROUND: the tables and the first round together: b builds entries
+// b and b + half and evaluates the round-1 pair at t = 0, 2.
+// q0 half; p9 S, p10 partials, p11 r_out, p12 msg.
+__device__ void body_p1_init_round(const Step& st, uint32_t tile, uint32_t ntiles) {
+  const Fr* W = P<const Fr*>(st, 0);
+  Fr* G = P<Fr*>(st, 1);
+  Fr* H = P<Fr*>(st, 2);
+  const uint64_t half = st.q[0];
   Fr acc[2] = {fr_zero(), fr_zero()};
-  for (uint64_t b = gtid(); b < half; b += gstride()) {
+  for (uint64_t b = GTID; b < half; b += GSTRIDE) {
     Fr g0, h0, g1, h1;
-    phase1_entry(W, xrow, xent, aU, bV, Cu, Cv, n, b, g0, h0);
-    phase1_entry(W, xrow, xent, aU, bV, Cu, Cv, n, b + half, g1, h1);
+    phase1_entry(st, b, g0, h0);
+    phase1_entry(st, b + half, g1, h1);
     stf(G, b, g0);
     stf(H, b, h0);
     stf(G, b + half, g1);
@@ -455,33 +415,44 @@ __global__ void __launch_bounds__(kBlock)
     const Fr w2 = fr_sub(fr_double(w1), w0), g2 = fr_sub(fr_double(g1), g0), h2 = fr_sub(fr_double(h1), h0);
     acc[1] = fr_add(acc[1], fr_add(fr_mul(w2, g2), h2));
   }
-  if (grid_reduce<2>(acc, partials, &S->counter) && threadIdx.x == 0)
-    finish_round(S, acc[0], acc[1], r_out, msg_out);
+  write_partial<2>(acc, P<Fr*>(st, 10), tile);
 }
 
-// ------------------------------------------------------- round kernels
+// Sum of the partials, then the Fiat-Shamir step in wave 0.
+__device__ void finish_reduced_round(const Fr* partials, uint32_t ntiles, DevState* S, Fr* r_out,
+                                     uint32_t* msg) {
+  Fr tot[2];
+  sum_partials<2>(partials, ntiles, tot);
+  broadcast_from_thread0<2>(tot);
+  if (threadIdx.x < 64) finish_round_wave(S, tot[0], tot[1], r_out, msg);
+}
+
+__device__ void finish_p1_init_round(const Step& st, uint32_t ntiles) {
+  finish_reduced_round(P<const Fr*>(st, 10), ntiles, P<DevState*>(st, 9), P<Fr*>(st, 11), P<uint32_t*>(st, 12));
+}
 
 // Fold (if `fold`) and evaluate one pair b of a round: the evaluated table has
 // 2*half entries; with folding the source has 4*half entries and the folded
 // entries b and b + half are written to dst.
 template <class Form>
-__device__ __forceinline__ void round_pair(const Tabs<Form::NT>& t, uint64_t b, uint64_t half,
-                                           bool fold, const Fr& r, Fr& acc0, Fr& acc2) {
+__device__ __forceinline__ void round_pair(const Fr* const* src, Fr* const* dst, uint64_t b,
+                                           uint64_t half, bool fold, const Fr& r, Fr& acc0,
+                                           Fr& acc2) {
   Fr x0[Form::NT], x2[Form::NT];
 #pragma unroll
   for (int k = 0; k < Form::NT; ++k) {
     Fr lo, hi;
     if (fold) {
       const uint64_t m = 2 * half;
-      const Fr a0 = ldf(t.src[k], b), a1 = ldf(t.src[k], b + m);
-      const Fr b0 = ldf(t.src[k], b + half), b1 = ldf(t.src[k], b + half + m);
+      const Fr a0 = ldf(src[k], b), a1 = ldf(src[k], b + m);
+      const Fr b0 = ldf(src[k], b + half), b1 = ldf(src[k], b + half + m);
       lo = fr_add(a0, fr_mul(r, fr_sub(a1, a0)));
       hi = fr_add(b0, fr_mul(r, fr_sub(b1, b0)));
-      stf(t.dst[k], b, lo);
-      stf(t.dst[k], b + half, hi);
+      stf(dst[k], b, lo);
+      stf(dst[k], b + half, hi);
     } else {
-      lo = ldf(t.src[k], b);
-      hi = ldf(t.src[k], b + half);
+      lo = ldf(src[k], b);
+      hi = ldf(src[k], b + half);
     }
     x0[k] = lo;
     x2[k] = fr_sub(fr_double(hi), lo);  // value at t = 2
@@ -490,31 +461,60 @@ __device__ __forceinline__ void round_pair(const Tabs<Form::NT>& t, uint64_t b, 
   Form::eval(x2, acc2);
 }
 
-// One sumcheck round over the whole grid (optional fold by the previous
-// challenge, evaluation at t = 0, 2, Fiat-Shamir in the last workgroup).
+// ST_ROUND_A / ST_ROUND_B: one sumcheck round (optional fold by the previous
+// challenge, evaluation at t = 0, 2); q0 half. Pointers: src[0..NT),
+// dst[NT..2NT), then rprev, S, partials, r_out, msg (RoundPtrs).
 template <class Form>
-__global__ void __launch_bounds__(kBlock)
-    k_round(Tabs<Form::NT> t, uint64_t half, const Fr* rprev, DevState* S, Fr* partials,
-            Fr* r_out, uint32_t* msg_out) {
+__device__ void body_round(const Step& st, uint32_t tile, uint32_t ntiles) {
+  using R = RoundPtrs<Form::NT>;
+  const Fr* src[Form::NT];
+  Fr* dst[Form::NT];
+#pragma unroll
+  for (int k = 0; k < Form::NT; ++k) {
+    src[k] = P<const Fr*>(st, k);
+    dst[k] = P<Fr*>(st, Form::NT + k);
+  }
+  const Fr* rprev = P<const Fr*>(st, R::kR);
   const bool fold = rprev != nullptr;
   const Fr r = fold ? ldf(rprev, 0) : fr_zero();
+  const uint64_t half = st.q[0];
   Fr acc[2] = {fr_zero(), fr_zero()};
-  for (uint64_t b = gtid(); b < half; b += gstride()) round_pair<Form>(t, b, half, fold, r, acc[0], acc[1]);
-  if (grid_reduce<2>(acc, partials, &S->counter) && threadIdx.x == 0)
-    finish_round(S, acc[0], acc[1], r_out, msg_out);
+  for (uint64_t b = GTID; b < half; b += GSTRIDE) round_pair<Form>(src, dst, b, half, fold, r, acc[0], acc[1]);
+  write_partial<2>(acc, P<Fr*>(st, R::kPart), tile);
+}
+template <class Form>
+__device__ void finish_round_step(const Step& st, uint32_t ntiles) {
+  using R = RoundPtrs<Form::NT>;
+  finish_reduced_round(P<const Fr*>(st, R::kPart), ntiles, P<DevState*>(st, R::kS), P<Fr*>(st, R::kROut),
+                       P<uint32_t*>(st, R::kMsg));
 }
 
-// The remaining rounds of a phase in one workgroup, then the final fold.
-// `size` is the table size before the pending fold (if any). Round messages go
-// to msg (24 words each) and challenges to r_out[0..rounds); the final value
-// of table 0 is stored in *final_out and, if proof_value is not null, written
-// to the proof and absorbed.
+// ST_TAIL_A / ST_TAIL_B: the remaining u0 rounds of a phase in one workgroup,
+// then the final fold. q0 = table size before the pending fold (if any).
+// Pointers: src, dst, rpending, S, r_out, msg, final_out, proof_value. The
+// final value of table 0 is stored in *final_out and, if proof_value is not
+// null, written to the proof and absorbed.
 template <class Form>
-__global__ void __launch_bounds__(kBlock)
-    k_tail(Tabs<Form::NT> t, uint64_t size, const Fr* rpending, uint32_t rounds, DevState* S,
-           Fr* r_out, uint32_t* msg, Fr* final_out, uint32_t* proof_value) {
+__device__ void body_tail(const Step& st, uint32_t, uint32_t) {
+  constexpr int NT = Form::NT;
+  const Fr* src[NT];
+  Fr* dst[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    src[k] = P<const Fr*>(st, k);
+    dst[k] = P<Fr*>(st, NT + k);
+  }
+  const Fr* rpending = P<const Fr*>(st, 2 * NT);
+  DevState* S = P<DevState*>(st, 2 * NT + 1);
+  Fr* r_out = P<Fr*>(st, 2 * NT + 2);
+  uint32_t* msg = P<uint32_t*>(st, 2 * NT + 3);
+  Fr* final_out = P<Fr*>(st, 2 * NT + 4);
+  uint32_t* proof_value = P<uint32_t*>(st, 2 * NT + 5);
+  uint64_t size = st.q[0];
+  const uint32_t rounds = st.u[0];
   __shared__ Fr r_sh;
   bool fold = rpending != nullptr;
+  __syncthreads();
   if (threadIdx.x == 0) r_sh = fold ? ldf(rpending, 0) : fr_zero();
   __syncthreads();
   for (uint32_t j = 0; j < rounds; ++j) {
@@ -522,42 +522,48 @@ __global__ void __launch_bounds__(kBlock)
     const uint64_t half = eval_size / 2;
     const Fr r = r_sh;
     Fr acc[2] = {fr_zero(), fr_zero()};
-    for (uint64_t b = threadIdx.x; b < half; b += kBlock) round_pair<Form>(t, b, half, fold, r, acc[0], acc[1]);
+    for (uint64_t b = threadIdx.x; b < half; b += kBlock) round_pair<Form>(src, dst, b, half, fold, r, acc[0], acc[1]);
     block_reduce<2>(acc);
-    if (threadIdx.x == 0) {
-      finish_round(S, acc[0], acc[1], r_out + j, msg + 24 * j);
-      r_sh = ldf(r_out + j, 0);
+    broadcast_from_thread0<2>(acc);
+    if (threadIdx.x < 64) {
+      finish_round_wave(S, acc[0], acc[1], r_out + j, msg + 24 * j);
+      if (threadIdx.x == 0) r_sh = ldf(r_out + j, 0);
     }
     __syncthreads();
     if (fold) {
 #pragma unroll
-      for (int k = 0; k < Form::NT; ++k) t.src[k] = t.dst[k];
+      for (int k = 0; k < NT; ++k) src[k] = dst[k];
     }
     fold = true;
     size = eval_size;
   }
   if (fold) {  // size is 2 here
-    if (threadIdx.x < Form::NT) {
+    if (threadIdx.x < NT) {
       const int k = threadIdx.x;
       const Fr r = r_sh;
-      const Fr a0 = ldf(t.src[k], 0), a1 = ldf(t.src[k], 1);
-      stf(t.dst[k], 0, fr_add(a0, fr_mul(r, fr_sub(a1, a0))));
+      const Fr a0 = ldf(src[k], 0), a1 = ldf(src[k], 1);
+      stf(dst[k], 0, fr_add(a0, fr_mul(r, fr_sub(a1, a0))));
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const Fr v = ldf(fold ? t.dst[0] : t.src[0], 0);
+    const Fr v = ldf(fold ? dst[0] : src[0], 0);
     if (proof_value) finish_value(S, v, final_out, proof_value);
     else *final_out = v;
   }
 }
 
-// U[c] = Cu[c] EC[c], V[c] = Cv[c] EC[c]; SU, SV = their sums (one workgroup).
-__global__ void __launch_bounds__(kBlock)
-    k_copy_weights(const Fr* Cu, const Fr* Cv, const Fr* EC, Fr* U, Fr* V, uint64_t ncopies,
-                   DevState* S) {
+// ST_COPY_WEIGHTS: U[c] = Cu[c] EC[c], V[c] = Cv[c] EC[c]; SU, SV their sums
+// (one workgroup). p0 Cu, p1 Cv, p2 EC, p3 U, p4 V, p5 S, q0 ncop.
+__device__ void body_copy_weights(const Step& st, uint32_t, uint32_t) {
+  const Fr* Cu = P<const Fr*>(st, 0);
+  const Fr* Cv = P<const Fr*>(st, 1);
+  const Fr* EC = P<const Fr*>(st, 2);
+  Fr* U = P<Fr*>(st, 3);
+  Fr* V = P<Fr*>(st, 4);
+  DevState* S = P<DevState*>(st, 5);
   Fr acc[2] = {fr_zero(), fr_zero()};
-  for (uint64_t c = threadIdx.x; c < ncopies; c += kBlock) {
+  for (uint64_t c = threadIdx.x; c < st.q[0]; c += kBlock) {
     const Fr ec = ldf(EC, c);
     const Fr u = fr_mul(ldf(Cu, c), ec), v = fr_mul(ldf(Cv, c), ec);
     stf(U, c, u);
@@ -572,17 +578,20 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// Phase-2 sub-circuit tables over y (thread per y), the copy factors kept apart:
+// ST_P2_TABLES: phase-2 sub-circuit tables over y, the copy factors kept apart:
 //   M[y,c] = U[c] Ma[y] + V[c] Mb[y],  A[y,c] = U[c] Aa[y] + V[c] Ab[y]
 //   Ma[y] = sum_{MUL z: y_z=y} aU[z] EL[x_z] (Mb with bV; Aa, Ab over ADD gates)
 //   Fa = vx Ma + Aa, Fb = vx Mb + Ab, Ka = vx Aa, Kb = vx Ab, Ks = SU Ka + SV Kb.
-__global__ void __launch_bounds__(kBlock)
-    k_phase2_tables(const uint32_t* __restrict__ yrow, const uint2* __restrict__ yent,
-                    const Fr* __restrict__ aU, const Fr* __restrict__ bV,
-                    const Fr* __restrict__ EL, const DevState* S, Fr* Fa, Fr* Fb, Fr* Ka,
-                    Fr* Kb, Fr* Ks, uint64_t count) {
+// p0 yrow, p1 yent, p2 aU, p3 bV, p4 EL, p5 S, p6 Fa, p7 Fb, p8 Ka, p9 Kb, p10 Ks, q0 count.
+__device__ void body_p2_tables(const Step& st, uint32_t tile, uint32_t ntiles) {
+  const uint32_t* __restrict__ yrow = P<const uint32_t*>(st, 0);
+  const uint2* __restrict__ yent = P<const uint2*>(st, 1);
+  const Fr* __restrict__ aU = P<const Fr*>(st, 2);
+  const Fr* __restrict__ bV = P<const Fr*>(st, 3);
+  const Fr* __restrict__ EL = P<const Fr*>(st, 4);
+  const DevState* S = P<const DevState*>(st, 5);
   const Fr vx = S->vx, su = S->su, sv = S->sv;
-  for (uint64_t y = gtid(); y < count; y += gstride()) {
+  for (uint64_t y = GTID; y < st.q[0]; y += GSTRIDE) {
     Fr ma = fr_zero(), mb = fr_zero(), aa = fr_zero(), ab = fr_zero();
     const uint32_t k1 = yrow[y + 1];
     for (uint32_t k = yrow[y]; k < k1; ++k) {
@@ -599,100 +608,125 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
     const Fr ka = fr_mul(vx, aa), kb = fr_mul(vx, ab);
-    stf(Fa, y, fr_add(fr_mul(vx, ma), aa));
-    stf(Fb, y, fr_add(fr_mul(vx, mb), ab));
-    stf(Ka, y, ka);
-    stf(Kb, y, kb);
-    stf(Ks, y, fr_add(fr_mul(su, ka), fr_mul(sv, kb)));
+    stf(P<Fr*>(st, 6), y, fr_add(fr_mul(vx, ma), aa));
+    stf(P<Fr*>(st, 7), y, fr_add(fr_mul(vx, mb), ab));
+    stf(P<Fr*>(st, 8), y, ka);
+    stf(P<Fr*>(st, 9), y, kb);
+    stf(P<Fr*>(st, 10), y, fr_add(fr_mul(su, ka), fr_mul(sv, kb)));
   }
 }
 
-// Row sums over the copies: P[y] = sum_c U[c] W[y,c], Q[y] = sum_c V[c] W[y,c].
-// A row of 2^n entries is handled by tpr = min(256, 2^n) threads.
-__global__ void __launch_bounds__(kBlock)
-    k_copy_contract(const Fr* __restrict__ W, const Fr* __restrict__ U, const Fr* __restrict__ V,
-                    Fr* __restrict__ P, Fr* __restrict__ Q, uint32_t n, uint64_t rows) {
+// ST_COPY_CONTRACT: row sums over the copies, P[y] = sum_c U[c] W[y,c],
+// Q[y] = sum_c V[c] W[y,c]. A row of 2^n entries is handled by
+// tpr = min(256, 2^n) threads; tile t covers rows t * (256 / tpr) onwards.
+// p0 W, p1 U, p2 V, p3 P, p4 Q, u0 n, q0 rows.
+__device__ void body_copy_contract(const Step& st, uint32_t tile, uint32_t ntiles) {
   __shared__ Fr sp[kBlock], sq[kBlock];
+  const Fr* __restrict__ W = P<const Fr*>(st, 0);
+  const Fr* __restrict__ U = P<const Fr*>(st, 1);
+  const Fr* __restrict__ V = P<const Fr*>(st, 2);
+  const uint32_t n = st.u[0];
+  const uint64_t rows = st.q[0];
   const uint32_t tpr_log = n < 8 ? n : 8;
   const uint32_t tpr = 1u << tpr_log;
-  const uint64_t row = (uint64_t)blockIdx.x * (kBlock >> tpr_log) + (threadIdx.x >> tpr_log);
   const uint32_t lane = threadIdx.x & (tpr - 1);
-  Fr p = fr_zero(), q = fr_zero();
-  if (row < rows) {
-    const uint64_t ncop = 1ull << n;
-    for (uint64_t c = lane; c < ncop; c += tpr) {
-      const Fr w = ldf(W, (row << n) | c);
-      p = fr_add(p, fr_mul(ldf(U, c), w));
-      q = fr_add(q, fr_mul(ldf(V, c), w));
-    }
-  }
-  sp[threadIdx.x] = p;
-  sq[threadIdx.x] = q;
-  __syncthreads();
-  for (uint32_t s = tpr / 2; s >= 1; s >>= 1) {
-    if (lane < s) {
-      sp[threadIdx.x] = fr_add(sp[threadIdx.x], sp[threadIdx.x + s]);
-      sq[threadIdx.x] = fr_add(sq[threadIdx.x], sq[threadIdx.x + s]);
+  const uint64_t rows_per_tile = kBlock >> tpr_log;
+  for (uint64_t base = (uint64_t)tile * rows_per_tile; base < rows; base += (uint64_t)ntiles * rows_per_tile) {
+    const uint64_t row = base + (threadIdx.x >> tpr_log);
+    Fr p = fr_zero(), q = fr_zero();
+    if (row < rows) {
+      const uint64_t ncop = 1ull << n;
+      for (uint64_t c = lane; c < ncop; c += tpr) {
+        const Fr w = ldf(W, (row << n) | c);
+        p = fr_add(p, fr_mul(ldf(U, c), w));
+        q = fr_add(q, fr_mul(ldf(V, c), w));
+      }
     }
     __syncthreads();
-  }
-  if (lane == 0 && row < rows) {
-    stf(P, row, sp[threadIdx.x]);
-    stf(Q, row, sq[threadIdx.x]);
+    sp[threadIdx.x] = p;
+    sq[threadIdx.x] = q;
+    __syncthreads();
+    for (uint32_t s = tpr / 2; s >= 1; s >>= 1) {
+      if (lane < s) {
+        sp[threadIdx.x] = fr_add(sp[threadIdx.x], sp[threadIdx.x + s]);
+        sq[threadIdx.x] = fr_add(sq[threadIdx.x], sq[threadIdx.x + s]);
+      }
+      __syncthreads();
+    }
+    if (lane == 0 && row < rows) {
+      stf(P<Fr*>(st, 3), row, sp[threadIdx.x]);
+      stf(P<Fr*>(st, 4), row, sq[threadIdx.x]);
+    }
   }
 }
 
-// Column sums over the sub-circuit variables, first stage:
-// part[c * R + k] = sum_{y in chunk k} EqR[y] W[y,c] (R = ychunks chunks of rows),
-// one thread per (column, chunk); each column's partials are contiguous.
-__global__ void __launch_bounds__(kBlock)
-    k_local_contract(const Fr* __restrict__ W, const Fr* __restrict__ EqR, Fr* __restrict__ part,
-                     uint32_t n, uint64_t rows, uint32_t ychunks) {
-  const uint64_t ncop = 1ull << n;
-  const uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  const uint32_t k = blockIdx.y;
-  if (c >= ncop) return;
-  const uint64_t per = (rows + ychunks - 1) / ychunks;
-  const uint64_t y0 = k * per, y1 = (y0 + per < rows) ? y0 + per : rows;
-  Fr acc = fr_zero();
-  for (uint64_t y = y0; y < y1; ++y) acc = fr_add(acc, fr_mul(ldf(EqR, y), ldf(W, (y << n) | c)));
-  stf(part, c * ychunks + k, acc);
+// ST_LOCAL_CONTRACT: column sums over the sub-circuit variables, first stage:
+// part[c * R + k] = sum_{y in chunk k} EqR[y] W[y,c] for R = u1 chunks of rows;
+// one thread per (column, chunk), tile t = column block (t % xb) and chunk (t / xb).
+// p0 W, p1 EqR, p2 part, u0 n, u1 R, q0 rows.
+__device__ void body_local_contract(const Step& st, uint32_t tile, uint32_t ntiles) {
+  const Fr* __restrict__ W = P<const Fr*>(st, 0);
+  const Fr* __restrict__ EqR = P<const Fr*>(st, 1);
+  Fr* __restrict__ part = P<Fr*>(st, 2);
+  const uint32_t n = st.u[0], R = st.u[1];
+  const uint64_t rows = st.q[0], ncop = 1ull << n;
+  const uint64_t xb = (ncop + kBlock - 1) / kBlock;
+  for (uint64_t t = tile; t < xb * R; t += ntiles) {
+    const uint64_t c = (t % xb) * kBlock + threadIdx.x;
+    const uint64_t k = t / xb;
+    if (c >= ncop) continue;
+    const uint64_t per = (rows + R - 1) / R;
+    const uint64_t y0 = k * per, y1 = (y0 + per < rows) ? y0 + per : rows;
+    Fr acc = fr_zero();
+    for (uint64_t y = y0; y < y1; ++y) acc = fr_add(acc, fr_mul(ldf(EqR, y), ldf(W, (y << n) | c)));
+    stf(part, c * R + k, acc);
+  }
 }
 
-// Second stage: the copy tables of phase 2. A column's R partials are summed
+// ST_COPY_TABLES: the copy tables of phase 2. A column's R partials are summed
 // by tpc = min(256, R) threads:
 // Wc[c] = sum_k part[c*R + k], Fc[c] = U[c] Fa~ + V[c] Fb~, Kc[c] = U[c] Ka~ + V[c] Kb~.
-__global__ void __launch_bounds__(kBlock)
-    k_copy_tables(const Fr* __restrict__ part, uint32_t ychunks, const Fr* __restrict__ U,
-                  const Fr* __restrict__ V, const Fr* fa_f, const Fr* fb_f, const DevState* S,
-                  Fr* Wc, Fr* Fc, Fr* Kc, uint64_t ncop) {
+// p0 part, p1 U, p2 V, p3 fa_f, p4 fb_f, p5 S, p6 Wc, p7 Fc, p8 Kc, u0 R, q0 ncop.
+__device__ void body_copy_tables(const Step& st, uint32_t tile, uint32_t ntiles) {
   __shared__ Fr sw[kBlock];
-  const uint32_t tpc_log = 31 - __clz(ychunks < kBlock ? ychunks : kBlock);
+  const Fr* __restrict__ part = P<const Fr*>(st, 0);
+  const uint32_t R = st.u[0];
+  const uint64_t ncop = st.q[0];
+  const uint32_t tpc_log = 31 - __clz(R < (uint32_t)kBlock ? R : (uint32_t)kBlock);
   const uint32_t tpc = 1u << tpc_log;
-  const uint64_t c = (uint64_t)blockIdx.x * (kBlock >> tpc_log) + (threadIdx.x >> tpc_log);
   const uint32_t lane = threadIdx.x & (tpc - 1);
-  Fr w = fr_zero();
-  if (c < ncop)
-    for (uint32_t k = lane; k < ychunks; k += tpc) w = fr_add(w, ldf(part, c * ychunks + k));
-  sw[threadIdx.x] = w;
-  __syncthreads();
-  for (uint32_t s = tpc / 2; s >= 1; s >>= 1) {
-    if (lane < s) sw[threadIdx.x] = fr_add(sw[threadIdx.x], sw[threadIdx.x + s]);
+  const uint64_t cols_per_tile = kBlock >> tpc_log;
+  const DevState* S = P<const DevState*>(st, 5);
+  for (uint64_t base = (uint64_t)tile * cols_per_tile; base < ncop; base += (uint64_t)ntiles * cols_per_tile) {
+    const uint64_t c = base + (threadIdx.x >> tpc_log);
+    Fr w = fr_zero();
+    if (c < ncop)
+      for (uint32_t k = lane; k < R; k += tpc) w = fr_add(w, ldf(part, c * R + k));
     __syncthreads();
-  }
-  if (lane == 0 && c < ncop) {
-    const Fr u = ldf(U, c), v = ldf(V, c);
-    stf(Wc, c, sw[threadIdx.x]);
-    stf(Fc, c, fr_add(fr_mul(u, *fa_f), fr_mul(v, *fb_f)));
-    stf(Kc, c, fr_add(fr_mul(u, S->ka_f), fr_mul(v, S->kb_f)));
+    sw[threadIdx.x] = w;
+    __syncthreads();
+    for (uint32_t s = tpc / 2; s >= 1; s >>= 1) {
+      if (lane < s) sw[threadIdx.x] = fr_add(sw[threadIdx.x], sw[threadIdx.x + s]);
+      __syncthreads();
+    }
+    if (lane == 0 && c < ncop) {
+      const Fr u = ldf(P<const Fr*>(st, 1), c), v = ldf(P<const Fr*>(st, 2), c);
+      stf(P<Fr*>(st, 6), c, sw[threadIdx.x]);
+      stf(P<Fr*>(st, 7), c, fr_add(fr_mul(u, *P<const Fr*>(st, 3)), fr_mul(v, *P<const Fr*>(st, 4))));
+      stf(P<Fr*>(st, 8), c, fr_add(fr_mul(u, S->ka_f), fr_mul(v, S->kb_f)));
+    }
   }
 }
 
-// Ka~, Kb~ at the phase-2 local point: dot products with EqR (one workgroup).
-__global__ void __launch_bounds__(kBlock)
-    k_local_values(const Fr* EqR, const Fr* Ka, const Fr* Kb, uint64_t rows, DevState* S) {
+// ST_LOCAL_VALUES: Ka~, Kb~ at the phase-2 sub-circuit point: dot products with
+// EqR (one workgroup). p0 EqR, p1 Ka, p2 Kb, p3 S, q0 rows.
+__device__ void body_local_values(const Step& st, uint32_t, uint32_t) {
+  const Fr* EqR = P<const Fr*>(st, 0);
+  const Fr* Ka = P<const Fr*>(st, 1);
+  const Fr* Kb = P<const Fr*>(st, 2);
+  DevState* S = P<DevState*>(st, 3);
   Fr acc[2] = {fr_zero(), fr_zero()};
-  for (uint64_t y = threadIdx.x; y < rows; y += kBlock) {
+  for (uint64_t y = threadIdx.x; y < st.q[0]; y += kBlock) {
     const Fr e = ldf(EqR, y);
     acc[0] = fr_add(acc[0], fr_mul(e, ldf(Ka, y)));
     acc[1] = fr_add(acc[1], fr_mul(e, ldf(Kb, y)));
@@ -704,8 +738,11 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// ABI plumbing: transcript state bytes <-> device state, canonical <-> Montgomery scalars.
-__global__ void k_state_export(const DevState* S, uint8_t* out) {
+// ST_STATE_EXPORT / ST_STATE_IMPORT: transcript state bytes <-> device state.
+// p0 S, p1 32-byte buffer.
+__device__ void body_state_export(const Step& st, uint32_t, uint32_t) {
+  const DevState* S = P<const DevState*>(st, 0);
+  uint8_t* out = P<uint8_t*>(st, 1);
   if (threadIdx.x < 8) {
     const uint32_t h = S->st[threadIdx.x];
     out[4 * threadIdx.x + 0] = (uint8_t)(h >> 24);
@@ -714,8 +751,9 @@ __global__ void k_state_export(const DevState* S, uint8_t* out) {
     out[4 * threadIdx.x + 3] = (uint8_t)h;
   }
 }
-
-__global__ void k_state_import(DevState* S, const uint8_t* in) {
+__device__ void body_state_import(const Step& st, uint32_t, uint32_t) {
+  DevState* S = P<DevState*>(st, 0);
+  const uint8_t* in = P<const uint8_t*>(st, 1);
   if (threadIdx.x < 8) {
     const uint8_t* b = in + 4 * threadIdx.x;
     S->st[threadIdx.x] = ((uint32_t)b[0] << 24) | ((uint32_t)b[1] << 16) | ((uint32_t)b[2] << 8) | b[3];
@@ -723,166 +761,286 @@ __global__ void k_state_import(DevState* S, const uint8_t* in) {
   if (threadIdx.x == 0) S->counter = 0;
 }
 
-// ------------------------------------------------------------ launchers
+#undef GTID
+#undef GSTRIDE
 
-static inline uint32_t grid_for(uint64_t n, uint32_t cap) {
+// Runs tile `tile` of a step; for reduction steps the last tile (by the
+// counter in the proof's state) also runs the finisher. Used by the batch kernel.
+__device__ void run_step_tile(const Step& st, uint32_t tile, uint32_t ntiles) {
+  uint32_t* counter = nullptr;
+  switch (st.type) {
+    case ST_WSUM: counter = &P<DevState*>(st, 4)->counter; break;
+    case ST_P1_INIT_ROUND: counter = &P<DevState*>(st, 9)->counter; break;
+    case ST_ROUND_A: counter = &P<DevState*>(st, RoundPtrs<3>::kS)->counter; break;
+    case ST_ROUND_B: counter = &P<DevState*>(st, RoundPtrs<5>::kS)->counter; break;
+    default: break;
+  }
+  switch (st.type) {
+    case ST_TO_MONT: body_to_mont(st, tile, ntiles); break;
+    case ST_FROM_MONT: body_from_mont(st, tile, ntiles); break;
+    case ST_FORWARD: body_forward(st, tile, ntiles); break;
+    case ST_DIGEST: body_digest(st, tile, ntiles); break;
+    case ST_TRANSCRIPT_BEGIN: body_transcript_begin(st, tile, ntiles); break;
+    case ST_SQUEEZE: body_squeeze(st, tile, ntiles); break;
+    case ST_LAYER_BEGIN: body_layer_begin(st, tile, ntiles); break;
+    case ST_EQ: body_eq(st, tile, ntiles); break;
+    case ST_WSUM:
+      body_wsum(st, tile, ntiles);
+      if (last_tile(counter, ntiles)) finish_wsum(st, ntiles);
+      break;
+    case ST_P1_INIT: body_p1_init(st, tile, ntiles); break;
+    case ST_P1_INIT_ROUND:
+      body_p1_init_round(st, tile, ntiles);
+      if (last_tile(counter, ntiles)) finish_p1_init_round(st, ntiles);
+      break;
+    case ST_ROUND_A:
+      body_round<FormA>(st, tile, ntiles);
+      if (last_tile(counter, ntiles)) finish_round_step<FormA>(st, ntiles);
+      break;
+    case ST_ROUND_B:
+      body_round<FormB>(st, tile, ntiles);
+      if (last_tile(counter, ntiles)) finish_round_step<FormB>(st, ntiles);
+      break;
+    case ST_TAIL_A: body_tail<FormA>(st, tile, ntiles); break;
+    case ST_TAIL_B: body_tail<FormB>(st, tile, ntiles); break;
+    case ST_COPY_WEIGHTS: body_copy_weights(st, tile, ntiles); break;
+    case ST_P2_TABLES: body_p2_tables(st, tile, ntiles); break;
+    case ST_COPY_CONTRACT: body_copy_contract(st, tile, ntiles); break;
+    case ST_LOCAL_CONTRACT: body_local_contract(st, tile, ntiles); break;
+    case ST_COPY_TABLES: body_copy_tables(st, tile, ntiles); break;
+    case ST_LOCAL_VALUES: body_local_values(st, tile, ntiles); break;
+    case ST_STATE_EXPORT: body_state_export(st, tile, ntiles); break;
+    case ST_STATE_IMPORT: body_state_import(st, tile, ntiles); break;
+    default: break;
+  }
+}
+
+// ------------------------------------------------------------ plain kernels
+
+// One kernel per step type, so each is compiled with only the registers its
+// own body needs. The counter of a reduction step lives in the proof's state.
+#define GKR_PLAIN_KERNEL(NAME, TYPE)                                              \
+  __global__ void __launch_bounds__(kBlock) NAME(Step st) {                       \
+    run_step_tile_##TYPE(st, blockIdx.x, gridDim.x);                              \
+  }
+
+#define GKR_SIMPLE(TYPE, BODY) \
+  __device__ __forceinline__ void run_step_tile_##TYPE(const Step& st, uint32_t t, uint32_t n) { BODY(st, t, n); }
+
+GKR_SIMPLE(to_mont, body_to_mont)
+GKR_SIMPLE(from_mont, body_from_mont)
+GKR_SIMPLE(forward, body_forward)
+GKR_SIMPLE(digest, body_digest)
+GKR_SIMPLE(transcript_begin, body_transcript_begin)
+GKR_SIMPLE(squeeze, body_squeeze)
+GKR_SIMPLE(layer_begin, body_layer_begin)
+GKR_SIMPLE(eq, body_eq)
+GKR_SIMPLE(p1_init, body_p1_init)
+GKR_SIMPLE(tail_a, body_tail<FormA>)
+GKR_SIMPLE(tail_b, body_tail<FormB>)
+GKR_SIMPLE(copy_weights, body_copy_weights)
+GKR_SIMPLE(p2_tables, body_p2_tables)
+GKR_SIMPLE(copy_contract, body_copy_contract)
+GKR_SIMPLE(local_contract, body_local_contract)
+GKR_SIMPLE(copy_tables, body_copy_tables)
+GKR_SIMPLE(local_values, body_local_values)
+GKR_SIMPLE(state_export, body_state_export)
+GKR_SIMPLE(state_import, body_state_import)
+
+__device__ __forceinline__ void run_step_tile_wsum(const Step& st, uint32_t t, uint32_t n) {
+  body_wsum(st, t, n);
+  if (last_tile(&P<DevState*>(st, 4)->counter, n)) finish_wsum(st, n);
+}
+__device__ __forceinline__ void run_step_tile_p1_init_round(const Step& st, uint32_t t, uint32_t n) {
+  body_p1_init_round(st, t, n);
+  if (last_tile(&P<DevState*>(st, 9)->counter, n)) finish_p1_init_round(st, n);
+}
+__device__ __forceinline__ void run_step_tile_round_a(const Step& st, uint32_t t, uint32_t n) {
+  body_round<FormA>(st, t, n);
+  if (last_tile(&P<DevState*>(st, RoundPtrs<3>::kS)->counter, n)) finish_round_step<FormA>(st, n);
+}
+__device__ __forceinline__ void run_step_tile_round_b(const Step& st, uint32_t t, uint32_t n) {
+  body_round<FormB>(st, t, n);
+  if (last_tile(&P<DevState*>(st, RoundPtrs<5>::kS)->counter, n)) finish_round_step<FormB>(st, n);
+}
+
+GKR_PLAIN_KERNEL(k_to_mont, to_mont)
+GKR_PLAIN_KERNEL(k_from_mont, from_mont)
+GKR_PLAIN_KERNEL(k_forward, forward)
+GKR_PLAIN_KERNEL(k_digest, digest)
+GKR_PLAIN_KERNEL(k_transcript_begin, transcript_begin)
+GKR_PLAIN_KERNEL(k_squeeze, squeeze)
+GKR_PLAIN_KERNEL(k_layer_begin, layer_begin)
+GKR_PLAIN_KERNEL(k_eq, eq)
+GKR_PLAIN_KERNEL(k_wsum, wsum)
+GKR_PLAIN_KERNEL(k_p1_init, p1_init)
+GKR_PLAIN_KERNEL(k_p1_init_round, p1_init_round)
+GKR_PLAIN_KERNEL(k_round_a, round_a)
+GKR_PLAIN_KERNEL(k_round_b, round_b)
+GKR_PLAIN_KERNEL(k_tail_a, tail_a)
+GKR_PLAIN_KERNEL(k_tail_b, tail_b)
+GKR_PLAIN_KERNEL(k_copy_weights, copy_weights)
+GKR_PLAIN_KERNEL(k_p2_tables, p2_tables)
+GKR_PLAIN_KERNEL(k_copy_contract, copy_contract)
+GKR_PLAIN_KERNEL(k_local_contract, local_contract)
+GKR_PLAIN_KERNEL(k_copy_tables, copy_tables)
+GKR_PLAIN_KERNEL(k_local_values, local_values)
+GKR_PLAIN_KERNEL(k_state_export, state_export)
+GKR_PLAIN_KERNEL(k_state_import, state_import)
+
+// ------------------------------------------------------------ batch kernel
+
+// Persistent kernel over up to kMaxBatchJobs step programs. Job j's counters
+// (device memory) are ctr[0] = current step, ctr[1 + s] = tiles of step s
+// claimed, ctr[1 + nsteps + s] = tiles of step s done. A workgroup claims a
+// tile of some job's current step, runs it, and counts it done; the tile that
+// completes a step publishes the next one (release fence, then the store), and
+// the tile that completes a job's last step counts the job finished. Tiles
+// never wait on other tiles, so the kernel always drains: a workgroup leaves
+// when a scan finds no unfinished job, or once ctl[1] (stop) is set - when the
+// step budget is reached or, with stop_on_finish, when any job finishes. A
+// workgroup with no claimable tile while jobs are unfinished sleeps and scans
+// again; the tiles it waits for are running and never wait themselves. A
+// claimed tile is always run to the end, so a later launch continues exactly
+// where this one stopped. ctl[0] = jobs finished in this launch, ctl[2] =
+// steps completed.
+__global__ void __launch_bounds__(kBlock) k_batch(BatchArgs a) {
+  __shared__ uint32_t sh_job, sh_step, sh_tile, sh_state;  // state: 0 work, 1 none, 2 exit
+  __shared__ Step sh_st;
+  uint32_t* ctl = a.ctl;
+  const uint32_t njobs = a.njobs;
+  uint32_t start = (blockIdx.x * 2654435761u) % njobs;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      uint32_t state = 1;
+      if (__hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        state = 2;
+      } else {
+        bool unfinished = false;
+        for (uint32_t scan = 0; scan < njobs && state == 1; ++scan) {
+          const uint32_t j = (start + scan) % njobs;
+          const BatchJobDev& jb = a.jobs[j];
+          uint32_t* ctr = jb.ctr;
+          const uint32_t s = __hip_atomic_load(&ctr[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          if (s >= jb.nsteps) continue;
+          unfinished = true;
+          const uint32_t nt = jb.steps[s].ntiles;
+          if (__hip_atomic_load(&ctr[1 + s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= nt) continue;
+          const uint32_t t = atomicAdd(&ctr[1 + s], 1u);
+          if (t < nt) {
+            sh_job = j;
+            sh_step = s;
+            sh_tile = t;
+            state = 0;
+            start = j;  // stay with this job while it has tiles
+          }
+        }
+        if (!unfinished) state = 2;  // every job is finished
+      }
+      sh_state = state;
+    }
+    __syncthreads();
+    const uint32_t state = sh_state;
+    if (state == 2) break;
+    if (state == 1) {
+      if (threadIdx.x == 0) __builtin_amdgcn_s_sleep(8);
+      __syncthreads();
+      continue;
+    }
+    const uint32_t j = sh_job, s = sh_step, tile = sh_tile;
+    const BatchJobDev& jb = a.jobs[j];
+    // copy the step record to LDS (256-byte record, 4-byte words)
+    {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(&jb.steps[s]);
+      uint32_t* dst = reinterpret_cast<uint32_t*>(&sh_st);
+      for (uint32_t k = threadIdx.x; k < sizeof(Step) / 4; k += kBlock) dst[k] = src[k];
+    }
+    __threadfence();  // acquire: see the writes of the previous steps
+    __syncthreads();
+    run_step_tile(sh_st, tile, sh_st.ntiles);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();  // release this tile's writes
+      uint32_t* ctr = jb.ctr;
+      const uint32_t d = atomicAdd(&ctr[1 + jb.nsteps + s], 1u);
+      if (d == sh_st.ntiles - 1) {
+        __threadfence();
+        const uint32_t done_steps = atomicAdd(&ctl[2], 1u) + 1;
+        __hip_atomic_store(&ctr[0], s + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (s + 1 == jb.nsteps) {
+          atomicAdd(&ctl[0], 1u);
+          if (a.stop_on_finish) atomicExch(&ctl[1], 1u);
+        }
+        if (a.step_budget && done_steps >= a.step_budget) atomicExch(&ctl[1], 1u);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Zero a job's counters (n words) so its program runs from the start.
+__global__ void __launch_bounds__(kBlock) k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock) p[i] = v;
+}
+
+void launch_batch(const BatchArgs& a, uint32_t workgroups, hipStream_t s) {
+  const int tok = prof_begin(s);
+  k_batch<<<workgroups, kBlock, 0, s>>>(a);
+  if (tok >= 0) prof_end(tok, s, PC_BATCH, 0.0, 0.0);
+}
+
+void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
   uint64_t g = (n + kBlock - 1) / kBlock;
   if (g < 1) g = 1;
-  if (g > cap) g = cap;
-  return (uint32_t)g;
+  if (g > 4096) g = 4096;
+  k_fill_u32<<<(uint32_t)g, kBlock, 0, s>>>(p, n, v);
 }
 
-constexpr uint32_t kSweepBlocks = 65535u * 8;  // grid-stride cap of plain sweeps
-constexpr double kE = 32.0;                     // bytes per field element
-
-// Bracket a launch with the optional timing events of its kernel class.
-#define GKR_LAUNCH(cls, bytes, mulmods, stream, ...)            \
-  do {                                                          \
-    const int tok_ = prof_begin(stream);                        \
-    __VA_ARGS__;                                                \
-    if (tok_ >= 0) prof_end(tok_, stream, cls, bytes, mulmods); \
-  } while (0)
-
-void launch_to_mont(const gkr_fr* in, Fr* out, uint64_t n, hipStream_t s) {
-  GKR_LAUNCH(PC_CONVERT, 2 * kE * n, (double)n, s,
-             k_to_mont<<<grid_for(n, kSweepBlocks), kBlock, 0, s>>>(in, out, n));
-}
-void launch_from_mont(const Fr* in, gkr_fr* out, uint64_t n, hipStream_t s) {
-  GKR_LAUNCH(PC_CONVERT, 2 * kE * n, (double)n, s,
-             k_from_mont<<<grid_for(n, kSweepBlocks), kBlock, 0, s>>>(in, out, n));
-}
-void launch_forward(const Fr* W, Fr* V, const uint2* gates, uint32_t n, uint64_t count,
-                    uint64_t mul_gates, hipStream_t s) {
-  GKR_LAUNCH(PC_FORWARD, 3 * kE * count, (double)mul_gates, s,
-             k_forward<<<grid_for(count, kSweepBlocks), kBlock, 0, s>>>(W, V, gates, n, count));
-}
-void launch_digest_level(const uint32_t* in, uint64_t nwords, int swap, uint32_t* out,
-                         uint64_t nchunks, hipStream_t s) {
-  GKR_LAUNCH(PC_DIGEST, 4.0 * nwords + 32.0 * nchunks, 0.0, s,
-             k_digest_level<<<grid_for(nchunks, kSweepBlocks), kBlock, 0, s>>>(in, nwords, swap, out, nchunks));
-}
-void launch_transcript_begin(DevState* S, const Words8& seed_state, const Words8& circ,
-                             const uint32_t* din, const uint32_t* dout, hipStream_t s) {
-  GKR_LAUNCH(PC_TRANSCRIPT, 0.0, 0.0, s, k_transcript_begin<<<1, 64, 0, s>>>(S, seed_state, circ, din, dout));
-}
-void launch_squeeze(DevState* S, Fr* out, uint32_t count, hipStream_t s) {
-  GKR_LAUNCH(PC_TRANSCRIPT, 0.0, (double)count, s, k_squeeze<<<1, 64, 0, s>>>(S, out, count));
-}
-void launch_layer_begin(DevState* S, int first, const Fr* vu, const Fr* vv, hipStream_t s) {
-  GKR_LAUNCH(PC_TRANSCRIPT, 0.0, 4.0, s, k_layer_begin<<<1, 64, 0, s>>>(S, first, vu, vv));
-}
-void launch_eq_tables(const EqJobs& jobs, hipStream_t s) {
-  uint64_t total = 0;
-  double mm = 0;
-  for (int j = 0; j < jobs.count; ++j) {
-    total += 1ull << jobs.bits[j];
-    mm += (double)(1ull << jobs.bits[j]) * (jobs.bits[j] + 1);
+uint32_t batch_kernel_max_workgroups_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch, kBlock, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
   }
-  GKR_LAUNCH(PC_EQ, kE * total, mm, s, k_eq_tables<<<grid_for(total, 1u << 30), kBlock, 0, s>>>(jobs));
-}
-void launch_weighted_sum(const Fr* V, const Fr* A, const Fr* B, uint32_t n, uint64_t count,
-                         Fr* partials, uint32_t* counter, Fr* dst, uint32_t max_blocks, hipStream_t s) {
-  GKR_LAUNCH(PC_CLAIM, kE * count, 2.0 * count, s,
-             k_weighted_sum<<<grid_for(count, max_blocks), kBlock, 0, s>>>(V, A, B, n, count, partials, counter, dst));
-}
-void launch_phase1_init_round(const Fr* W, Fr* G, Fr* H, const LayerWiring& lw, const Fr* aU,
-                              const Fr* bV, const Fr* Cu, const Fr* Cv, uint32_t n, uint64_t half,
-                              uint64_t gates, DevState* S, Fr* partials, Fr* r_out, uint32_t* msg,
-                              uint32_t max_blocks, hipStream_t s) {
-  GKR_LAUNCH(PC_PHASE1_INIT, kE * (gates + 6.0 * half), 3.0 * gates + 2.0 * half, s,
-             k_phase1_init_round<<<grid_for(half, max_blocks), kBlock, 0, s>>>(W, G, H, lw.xrow, lw.xent, aU, bV, Cu, Cv, n, half, S, partials, r_out, msg));
-}
-void launch_phase1_init(const Fr* W, Fr* G, Fr* H, const LayerWiring& lw, const Fr* aU,
-                        const Fr* bV, const Fr* Cu, const Fr* Cv, uint32_t n, uint64_t count,
-                        uint64_t gates, hipStream_t s) {
-  GKR_LAUNCH(PC_PHASE1_INIT, kE * (gates + 2.0 * count), 3.0 * gates, s,
-             k_phase1_init<<<grid_for(count, kSweepBlocks), kBlock, 0, s>>>(W, G, H, lw.xrow, lw.xent, aU, bV, Cu, Cv, n, count));
+  return nb < 1 ? 1 : (uint32_t)nb;
 }
 
-// Algorithmic bytes and products of one round over `half` pairs of NT tables.
-static inline void round_work(int nt, int eval_products, uint64_t half, bool fold, double& bytes,
-                              double& mm) {
-  const double h = (double)half;
-  bytes += fold ? kE * nt * 6.0 * h : kE * nt * 2.0 * h;
-  mm += (fold ? 2.0 * nt * h : 0.0) + eval_products * 2.0 * h;
-}
+static const ProfClass kStepClass[ST_COUNT] = {
+    PC_CONVERT,        PC_CONVERT, PC_FORWARD, PC_DIGEST,        PC_TRANSCRIPT,    PC_TRANSCRIPT,
+    PC_TRANSCRIPT,     PC_EQ,      PC_CLAIM,   PC_PHASE1_INIT,   PC_PHASE1_INIT,   PC_ROUND_A,
+    PC_ROUND_B,        PC_TAIL_A,  PC_TAIL_B,  PC_SMALL,         PC_PHASE2_TABLES, PC_COPY_CONTRACT,
+    PC_LOCAL_CONTRACT, PC_SMALL,   PC_SMALL,   PC_SMALL,         PC_SMALL};
 
-template <class Form>
-void launch_round(const Tabs<Form::NT>& t, uint64_t half, const Fr* rprev, DevState* S,
-                  Fr* partials, Fr* r_out, uint32_t* msg, uint32_t max_blocks, hipStream_t s) {
-  double bytes = 0, mm = 0;
-  round_work(Form::NT, Form::NT == 3 ? 1 : 2, half, rprev != nullptr, bytes, mm);
-  GKR_LAUNCH(Form::NT == 3 ? PC_ROUND_A : PC_ROUND_B, bytes, mm, s,
-             k_round<Form><<<grid_for(half, max_blocks), kBlock, 0, s>>>(t, half, rprev, S, partials, r_out, msg));
-}
-template <class Form>
-void launch_tail(const Tabs<Form::NT>& t, uint64_t size, const Fr* rpending, uint32_t rounds,
-                 DevState* S, Fr* r_out, uint32_t* msg, Fr* final_out, uint32_t* proof_value,
-                 hipStream_t s) {
-  double bytes = 0, mm = 0;
-  bool fold = rpending != nullptr;
-  uint64_t sz = size;
-  for (uint32_t j = 0; j < rounds; ++j) {
-    const uint64_t eval = fold ? sz / 2 : sz;
-    round_work(Form::NT, Form::NT == 3 ? 1 : 2, eval / 2, fold, bytes, mm);
-    fold = true;
-    sz = eval;
+void launch_step(const Step& st, hipStream_t s) {
+  const int tok = prof_begin(s);
+  const dim3 grid(st.ntiles), block(kBlock);
+  switch (st.type) {
+    case ST_TO_MONT: k_to_mont<<<grid, block, 0, s>>>(st); break;
+    case ST_FROM_MONT: k_from_mont<<<grid, block, 0, s>>>(st); break;
+    case ST_FORWARD: k_forward<<<grid, block, 0, s>>>(st); break;
+    case ST_DIGEST: k_digest<<<grid, block, 0, s>>>(st); break;
+    case ST_TRANSCRIPT_BEGIN: k_transcript_begin<<<grid, block, 0, s>>>(st); break;
+    case ST_SQUEEZE: k_squeeze<<<grid, block, 0, s>>>(st); break;
+    case ST_LAYER_BEGIN: k_layer_begin<<<grid, block, 0, s>>>(st); break;
+    case ST_EQ: k_eq<<<grid, block, 0, s>>>(st); break;
+    case ST_WSUM: k_wsum<<<grid, block, 0, s>>>(st); break;
+    case ST_P1_INIT: k_p1_init<<<grid, block, 0, s>>>(st); break;
+    case ST_P1_INIT_ROUND: k_p1_init_round<<<grid, block, 0, s>>>(st); break;
+    case ST_ROUND_A: k_round_a<<<grid, block, 0, s>>>(st); break;
+    case ST_ROUND_B: k_round_b<<<grid, block, 0, s>>>(st); break;
+    case ST_TAIL_A: k_tail_a<<<grid, block, 0, s>>>(st); break;
+    case ST_TAIL_B: k_tail_b<<<grid, block, 0, s>>>(st); break;
+    case ST_COPY_WEIGHTS: k_copy_weights<<<grid, block, 0, s>>>(st); break;
+    case ST_P2_TABLES: k_p2_tables<<<grid, block, 0, s>>>(st); break;
+    case ST_COPY_CONTRACT: k_copy_contract<<<grid, block, 0, s>>>(st); break;
+    case ST_LOCAL_CONTRACT: k_local_contract<<<grid, block, 0, s>>>(st); break;
+    case ST_COPY_TABLES: k_copy_tables<<<grid, block, 0, s>>>(st); break;
+    case ST_LOCAL_VALUES: k_local_values<<<grid, block, 0, s>>>(st); break;
+    case ST_STATE_EXPORT: k_state_export<<<grid, block, 0, s>>>(st); break;
+    case ST_STATE_IMPORT: k_state_import<<<grid, block, 0, s>>>(st); break;
+    default: break;
   }
-  if (fold) mm += Form::NT;
-  GKR_LAUNCH(Form::NT == 3 ? PC_TAIL_A : PC_TAIL_B, bytes, mm, s,
-             k_tail<Form><<<1, kBlock, 0, s>>>(t, size, rpending, rounds, S, r_out, msg, final_out, proof_value));
-}
-template void launch_round<FormA>(const Tabs<3>&, uint64_t, const Fr*, DevState*, Fr*, Fr*, uint32_t*, uint32_t, hipStream_t);
-template void launch_round<FormB>(const Tabs<5>&, uint64_t, const Fr*, DevState*, Fr*, Fr*, uint32_t*, uint32_t, hipStream_t);
-template void launch_tail<FormA>(const Tabs<3>&, uint64_t, const Fr*, uint32_t, DevState*, Fr*, uint32_t*, Fr*, uint32_t*, hipStream_t);
-template void launch_tail<FormB>(const Tabs<5>&, uint64_t, const Fr*, uint32_t, DevState*, Fr*, uint32_t*, Fr*, uint32_t*, hipStream_t);
-
-void launch_copy_weights(const Fr* Cu, const Fr* Cv, const Fr* EC, Fr* U, Fr* V, uint64_t ncop,
-                         DevState* S, hipStream_t s) {
-  GKR_LAUNCH(PC_SMALL, 5 * kE * ncop, 2.0 * ncop, s, k_copy_weights<<<1, kBlock, 0, s>>>(Cu, Cv, EC, U, V, ncop, S));
-}
-void launch_phase2_tables(const LayerWiring& lw, const Fr* aU, const Fr* bV, const Fr* EL,
-                          const DevState* S, Fr* Fa, Fr* Fb, Fr* Ka, Fr* Kb, Fr* Ks, uint64_t count,
-                          uint64_t gates, hipStream_t s) {
-  GKR_LAUNCH(PC_PHASE2_TABLES, kE * (3.0 * gates + 5.0 * count), 2.0 * gates + 8.0 * count, s,
-             k_phase2_tables<<<grid_for(count, kSweepBlocks), kBlock, 0, s>>>(lw.yrow, lw.yent, aU, bV, EL, S, Fa, Fb, Ka, Kb, Ks, count));
-}
-void launch_copy_contract(const Fr* W, const Fr* U, const Fr* V, Fr* P, Fr* Q, uint32_t n,
-                          uint64_t rows, hipStream_t s) {
-  const uint32_t tpr_log = n < 8 ? n : 8;
-  const uint64_t rows_per_block = kBlock >> tpr_log;
-  const uint64_t grid = (rows + rows_per_block - 1) / rows_per_block;
-  const double elems = (double)(rows << n);
-  GKR_LAUNCH(PC_COPY_CONTRACT, kE * elems, 2.0 * elems, s,
-             k_copy_contract<<<(uint32_t)grid, kBlock, 0, s>>>(W, U, V, P, Q, n, rows));
-}
-void launch_local_contract(const Fr* W, const Fr* EqR, Fr* part, uint32_t n, uint64_t rows,
-                           uint32_t ychunks, hipStream_t s) {
-  const uint64_t ncop = 1ull << n;
-  dim3 grid((uint32_t)((ncop + kBlock - 1) / kBlock), ychunks);
-  const double elems = (double)(rows << n);
-  GKR_LAUNCH(PC_LOCAL_CONTRACT, kE * elems, elems, s,
-             k_local_contract<<<grid, kBlock, 0, s>>>(W, EqR, part, n, rows, ychunks));
-}
-void launch_copy_tables(const Fr* part, uint32_t ychunks, const Fr* U, const Fr* V, const Fr* fa_f,
-                        const Fr* fb_f, const DevState* S, Fr* Wc, Fr* Fc, Fr* Kc, uint64_t ncop,
-                        hipStream_t s) {
-  uint32_t tpc_log = 0;
-  while (tpc_log < 8 && (2u << tpc_log) <= ychunks) ++tpc_log;
-  const uint64_t cols_per_block = kBlock >> tpc_log;
-  const uint64_t grid = (ncop + cols_per_block - 1) / cols_per_block;
-  GKR_LAUNCH(PC_SMALL, kE * (ychunks + 5.0) * ncop, 4.0 * ncop, s,
-             k_copy_tables<<<(uint32_t)grid, kBlock, 0, s>>>(part, ychunks, U, V, fa_f, fb_f, S, Wc, Fc, Kc, ncop));
-}
-void launch_local_values(const Fr* EqR, const Fr* Ka, const Fr* Kb, uint64_t rows, DevState* S,
-                         hipStream_t s) {
-  GKR_LAUNCH(PC_SMALL, 3 * kE * rows, 2.0 * rows, s, k_local_values<<<1, kBlock, 0, s>>>(EqR, Ka, Kb, rows, S));
-}
-void launch_state_export(const DevState* S, uint8_t* out, hipStream_t s) {
-  GKR_LAUNCH(PC_SMALL, 0.0, 0.0, s, k_state_export<<<1, 64, 0, s>>>(S, out));
-}
-void launch_state_import(DevState* S, const uint8_t* in, hipStream_t s) {
-  GKR_LAUNCH(PC_SMALL, 0.0, 0.0, s, k_state_import<<<1, 64, 0, s>>>(S, in));
+  if (tok >= 0) prof_end(tok, s, kStepClass[st.type], st.bytes, st.mulmods);
 }
 
 }  // namespace gkr

@@ -1,4 +1,4 @@
-// Launchers of the GKR kernels (implemented in gkr_kernels.hip).
+// Step forms and launchers of the GKR kernels (implemented in gkr_kernels.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,12 +9,6 @@ namespace gkr {
 
 struct Words8 {
   uint32_t w[8];
-};
-
-template <int NT>
-struct Tabs {
-  const Fr* src[NT];
-  Fr* dst[NT];
 };
 
 // Phase 1 and the copy rounds of phase 2: sum_b W[b] G[b] + H[b]; tables (W, G, H).
@@ -34,56 +28,39 @@ struct FormB {
   }
 };
 
-struct EqJobs {
-  int count;
-  int bits[4];
-  const Fr* point[4];
-  const Fr* scale[4];  // nullptr = 1
-  Fr* out[4];
+// Pointer slots of round steps over NT tables: src[0..NT), dst[NT..2NT), then
+// the previous challenge (null: no fold), the proof state, the partials, the
+// challenge output and the message output.
+template <int NT>
+struct RoundPtrs {
+  static constexpr int kR = 2 * NT, kS = kR + 1, kPart = kR + 2, kROut = kR + 3, kMsg = kR + 4;
 };
 
-void launch_to_mont(const gkr_fr* in, Fr* out, uint64_t n, hipStream_t s);
-void launch_from_mont(const Fr* in, gkr_fr* out, uint64_t n, hipStream_t s);
-void launch_forward(const Fr* W, Fr* V, const uint2* gates, uint32_t n, uint64_t count,
-                    uint64_t mul_gates, hipStream_t s);
-void launch_digest_level(const uint32_t* in, uint64_t nwords, int swap, uint32_t* out, uint64_t nchunks,
-                         hipStream_t s);
-void launch_transcript_begin(DevState* S, const Words8& seed_state, const Words8& circ,
-                             const uint32_t* din, const uint32_t* dout, hipStream_t s);
-void launch_squeeze(DevState* S, Fr* out, uint32_t count, hipStream_t s);
-void launch_layer_begin(DevState* S, int first, const Fr* vu, const Fr* vv, hipStream_t s);
-void launch_eq_tables(const EqJobs& jobs, hipStream_t s);
-void launch_weighted_sum(const Fr* V, const Fr* A, const Fr* B, uint32_t n, uint64_t count,
-                         Fr* partials, uint32_t* counter, Fr* dst, uint32_t max_blocks, hipStream_t s);
-void launch_phase1_init(const Fr* W, Fr* G, Fr* H, const LayerWiring& lw, const Fr* aU,
-                        const Fr* bV, const Fr* Cu, const Fr* Cv, uint32_t n, uint64_t count,
-                        uint64_t gates, hipStream_t s);
-void launch_phase1_init_round(const Fr* W, Fr* G, Fr* H, const LayerWiring& lw, const Fr* aU,
-                              const Fr* bV, const Fr* Cu, const Fr* Cv, uint32_t n, uint64_t half,
-                              uint64_t gates, DevState* S, Fr* partials, Fr* r_out, uint32_t* msg,
-                              uint32_t max_blocks, hipStream_t s);
-template <class Form>
-void launch_round(const Tabs<Form::NT>& t, uint64_t half, const Fr* rprev, DevState* S,
-                  Fr* partials, Fr* r_out, uint32_t* msg, uint32_t max_blocks, hipStream_t s);
-template <class Form>
-void launch_tail(const Tabs<Form::NT>& t, uint64_t size, const Fr* rpending, uint32_t rounds,
-                 DevState* S, Fr* r_out, uint32_t* msg, Fr* final_out, uint32_t* proof_value,
-                 hipStream_t s);
-void launch_copy_weights(const Fr* Cu, const Fr* Cv, const Fr* EC, Fr* U, Fr* V, uint64_t ncop,
-                         DevState* S, hipStream_t s);
-void launch_phase2_tables(const LayerWiring& lw, const Fr* aU, const Fr* bV, const Fr* EL,
-                          const DevState* S, Fr* Fa, Fr* Fb, Fr* Ka, Fr* Kb, Fr* Ks, uint64_t count,
-                          uint64_t gates, hipStream_t s);
-void launch_copy_contract(const Fr* W, const Fr* U, const Fr* V, Fr* P, Fr* Q, uint32_t n,
-                          uint64_t rows, hipStream_t s);
-void launch_local_contract(const Fr* W, const Fr* EqR, Fr* part, uint32_t n, uint64_t rows,
-                           uint32_t ychunks, hipStream_t s);
-void launch_copy_tables(const Fr* part, uint32_t ychunks, const Fr* U, const Fr* V, const Fr* fa_f,
-                        const Fr* fb_f, const DevState* S, Fr* Wc, Fr* Fc, Fr* Kc, uint64_t ncop,
-                        hipStream_t s);
-void launch_local_values(const Fr* EqR, const Fr* Ka, const Fr* Kb, uint64_t rows, DevState* S,
-                         hipStream_t s);
-void launch_state_export(const DevState* S, uint8_t* out, hipStream_t s);
-void launch_state_import(DevState* S, const uint8_t* in, hipStream_t s);
+// Launch one step as its own kernel (grid = st.ntiles workgroups).
+void launch_step(const Step& st, hipStream_t s);
+
+// One job of the persistent batch kernel: its step program and counters
+// (ctr[0] current step, ctr[1..nsteps] claimed tiles, ctr[1+nsteps..] done tiles).
+struct BatchJobDev {
+  const Step* steps;
+  uint32_t* ctr;
+  uint32_t nsteps;
+  uint32_t pad;
+};
+
+constexpr uint32_t kMaxBatchJobs = 64;
+
+struct BatchArgs {
+  BatchJobDev jobs[kMaxBatchJobs];
+  uint32_t njobs;
+  uint32_t step_budget;     // 0 = no budget
+  uint32_t stop_on_finish;  // stop the launch when any job finishes
+  uint32_t pad;
+  uint32_t* ctl;            // [0] jobs finished, [1] stop, [2] steps completed, [3] spare
+};
+
+void launch_batch(const BatchArgs& a, uint32_t workgroups, hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+uint32_t batch_kernel_max_workgroups_per_cu();
 
 }  // namespace gkr

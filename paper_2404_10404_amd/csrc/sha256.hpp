@@ -48,16 +48,10 @@ GKR_HD Sha256State sha256_iv() {
   return s;
 }
 
-#if defined(__HIP_DEVICE_COMPILE__)
-#define GKR_SHA_FN static __device__ __attribute__((noinline))
-#else
-#define GKR_SHA_FN static inline
-#endif
-
 // One compression of a 16-word (big-endian) block into the chaining value.
 // The 64 rounds run as four passes of 16 unrolled rounds over a rolling
-// 16-word schedule, so the code stays small (one copy per kernel).
-GKR_SHA_FN Sha256State sha256_compress_v(Sha256State st, Sha256Block blk) {
+// 16-word schedule, so each inlined copy stays small.
+GKR_HD Sha256State sha256_compress_v(Sha256State st, Sha256Block blk) {
   uint32_t a = st.h[0], b = st.h[1], c = st.h[2], d = st.h[3];
   uint32_t e = st.h[4], f = st.h[5], g = st.h[6], h = st.h[7];
   for (int j = 0; j < 64; j += 16) {

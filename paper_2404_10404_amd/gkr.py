@@ -28,8 +28,8 @@ EXPORTS = (
     "gkr_last_error", "gkr_circuit_create", "gkr_circuit_destroy", "gkr_workspace_bytes",
     "gkr_proof_bytes", "gkr_layer_proof_bytes", "gkr_gate_layers", "gkr_prove_circuit",
     "gkr_transcript_init", "gkr_output_claim", "gkr_prove_layer", "gkr_verify",
-    "gkr_prove_batch", "gkr_batch_workspace_bytes", "gkr_set_tuning", "gkr_get_tuning",
-    "gkr_profile_enable", "gkr_profile_read",
+    "gkr_plan_create", "gkr_plan_destroy", "gkr_plan_reset", "gkr_run_batch", "gkr_plan_progress",
+    "gkr_prove_batch", "gkr_set_tuning", "gkr_get_tuning", "gkr_profile_enable", "gkr_profile_read",
 )
 
 
@@ -239,3 +239,93 @@ class Prover:
 
     def proof_bytes(self) -> bytes:
         return bytes(self.proof[: self.c.proof_bytes].cpu().numpy().tobytes())
+
+
+# ------------------------------------------------------------ batched proving
+
+class Job(ctypes.Structure):
+    _fields_ = [("circuit", _vp), ("d_inputs", _vp), ("seed", _u64), ("d_outputs", _vp), ("d_proof", _vp),
+                ("proof_cap", _sz), ("d_ws", _vp), ("ws_bytes", _sz)]
+
+
+def _batch_lib():
+    L = lib()
+    if not getattr(L, "_batch_ready", False):
+        L.gkr_plan_create.argtypes = [ctypes.POINTER(Job), ctypes.POINTER(_vp)]
+        L.gkr_plan_create.restype = _i32
+        L.gkr_plan_destroy.argtypes = [_vp]
+        L.gkr_plan_destroy.restype = None
+        L.gkr_plan_reset.argtypes = [_vp, _vp]
+        L.gkr_plan_reset.restype = _i32
+        L.gkr_run_batch.argtypes = [ctypes.POINTER(_vp), _u32, _vp, _u32, _u32, _u32, _vp]
+        L.gkr_run_batch.restype = _i32
+        L.gkr_plan_progress.argtypes = [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u32)]
+        L.gkr_plan_progress.restype = _i32
+        L.gkr_prove_batch.argtypes = [ctypes.POINTER(Job), _u32, _vp]
+        L.gkr_prove_batch.restype = _i32
+        L.gkr_set_tuning.argtypes = [_u32, _u32]
+        L.gkr_set_tuning.restype = _i32
+        L.gkr_get_tuning.argtypes = [ctypes.POINTER(_u32), ctypes.POINTER(_u32)]
+        L.gkr_get_tuning.restype = _i32
+        L._batch_ready = True
+    return L
+
+
+def make_job(c: Circuit, d_inputs, seed: int, d_outputs, d_proof, d_ws) -> Job:
+    return Job(c.handle.value, _ptr(d_inputs), seed & (2**64 - 1), _ptr(d_outputs), _ptr(d_proof),
+               d_proof.numel() * d_proof.element_size(), _ptr(d_ws), d_ws.numel() * d_ws.element_size())
+
+
+class Plan:
+    """A job's proof program recorded in device memory (gkr_plan_create)."""
+
+    def __init__(self, job: Job):
+        self.job = job
+        h = _vp()
+        _check(_batch_lib().gkr_plan_create(ctypes.byref(job), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def reset(self, stream=None):
+        _check(_batch_lib().gkr_plan_reset(self._h, _stream(stream)))
+
+    def progress(self) -> Tuple[int, int]:
+        d, t = _u32(0), _u32(0)
+        _check(_batch_lib().gkr_plan_progress(self._h, ctypes.byref(d), ctypes.byref(t)))
+        return d.value, t.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _batch_lib().gkr_plan_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_batch(plans: Sequence[Plan], d_ctl, workgroups: int = 0, step_budget: int = 0,
+              stop_on_finish: bool = False, stream=None):
+    arr = (_vp * len(plans))(*[p.handle.value for p in plans])
+    _check(_batch_lib().gkr_run_batch(arr, len(plans), _ptr(d_ctl), workgroups, step_budget,
+                                      1 if stop_on_finish else 0, _stream(stream)))
+
+
+def prove_batch(jobs: Sequence[Job], stream=None):
+    arr = (Job * len(jobs))(*jobs)
+    _check(_batch_lib().gkr_prove_batch(arr, len(jobs), _stream(stream)))
+
+
+def set_tuning(tail_log: int, max_round_blocks: int):
+    _check(_batch_lib().gkr_set_tuning(tail_log, max_round_blocks))
+
+
+def get_tuning() -> Tuple[int, int]:
+    a, b = _u32(0), _u32(0)
+    _check(_batch_lib().gkr_get_tuning(ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value

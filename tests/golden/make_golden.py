@@ -2,12 +2,14 @@
 
 Only the oracle and the seeded generator are used. Each file records the
 workload, the SHA-256 of the outputs and of the proof, and the proof itself
-(hex) for the smaller cases.
+(hex) for the smaller cases. "c4" proves the 64 jobs of the uneven batch
+(one oracle process per CPU) and stores each job's digests.
 
-    python tests/golden/make_golden.py c1 c2 c3slice
+    python tests/golden/make_golden.py c1 c2 c3slice c4
 """
 import hashlib
 import json
+import multiprocessing
 import os
 import sys
 import time
@@ -56,6 +58,32 @@ def make(name):
     print(name, "done in %.1f s" % (time.time() - t0), flush=True)
 
 
+def _batch_job(k):
+    spec = gs.batch_jobs_c4()[k]
+    wiring = gs.make_wiring(spec)
+    inputs = gs.elements_to_ints(gs.make_inputs(spec))
+    pt = op.prove(oc.Circuit.from_synth(spec, wiring), inputs, spec.seed)
+    return {
+        "job": k, "seed": spec.seed, "depth": spec.depth, "log_copies": spec.log_copies,
+        "log_sub_width": list(spec.log_sub_width),
+        "outputs_sha256": hashlib.sha256(encode_all(pt.outputs)).hexdigest(),
+        "proof_sha256": hashlib.sha256(pt.proof_bytes()).hexdigest(),
+    }
+
+
+def make_c4():
+    t0 = time.time()
+    jobs = gs.batch_jobs_c4()
+    order = sorted(range(len(jobs)), key=lambda k: -jobs[k].gate_layers)  # longest first
+    with multiprocessing.Pool(min(8, os.cpu_count() or 1)) as pool:
+        recs = pool.map(_batch_job, order, chunksize=1)
+    recs.sort(key=lambda r: r["job"])
+    with open(os.path.join(HERE, "c4_batch.json"), "w") as f:
+        json.dump({"workload": "c4", "writer": "tests/golden/make_golden.py (CPU oracle)",
+                   "oracle_seconds": round(time.time() - t0, 1), "jobs": recs}, f, indent=1)
+    print("c4 done in %.1f s" % (time.time() - t0), flush=True)
+
+
 if __name__ == "__main__":
     for n in sys.argv[1:] or ["c1"]:
-        make(n)
+        make_c4() if n == "c4" else make(n)
