@@ -184,6 +184,42 @@ def batched_comparison(gkr, steps, warmup):
     }
 
 
+def serving_comparison(gkr, njobs, max_slots, budget_gib, util=0.8):
+    """Poisson trace of the serving mix: plain one-at-a-time loop vs continuous batching."""
+    import torch
+
+    from paper_2404_10404_amd import serve
+    specs = gs.serving_jobs_c5(njobs)
+    reqs = []
+    for k, spec in enumerate(specs):
+        c = gkr.Circuit.from_synth(spec, gs.make_wiring(spec))
+        reqs.append(serve.Request(rid=k, circuit=c, inputs=gs.make_inputs(spec), seed=spec.seed, arrival=0.0,
+                                  gate_layers=spec.gate_layers))
+    # mean plain service time of the mix (all jobs back to back, after one warm-up job)
+    serve.serve_plain(reqs[:1], keep_proofs=False)
+    t0 = time.perf_counter()
+    serve.serve_plain(reqs, keep_proofs=False)
+    mean_service = (time.perf_counter() - t0) / len(reqs)
+    rate = util / mean_service
+    gaps = gs.poisson_gaps(len(reqs), rate)
+    t = 0.0
+    for r, g in zip(reqs, gaps):
+        t += float(g)
+        r.arrival = t
+    plain = serve.serve_plain(reqs, keep_proofs=True)
+    mixed = serve.serve(reqs, serve.GpuExecutor(keep_proofs=True), max_slots=max_slots,
+                        budget_bytes=int(budget_gib * (1 << 30)))
+    same = all(mixed[r.rid].proof == plain[r.rid].proof and mixed[r.rid].proof is not None for r in reqs)
+    torch.cuda.synchronize()
+    return {
+        "workload": "%d jobs: log2 gates/layer uniform in [12,22], depth in [8,24], Poisson arrivals" % len(reqs),
+        "arrival_rate_per_s": round(rate, 3), "mean_plain_service_s": round(mean_service, 5),
+        "max_slots": max_slots, "hbm_budget_gib": budget_gib,
+        "plain_loop": serve.summary(plain, reqs), "continuous_batching": serve.summary(mixed, reqs),
+        "proofs_identical_alone_and_in_mix": same,
+    }
+
+
 def golden_digest(workload):
     p = os.path.join(ROOT, "tests", "golden", "%s_proof.json" % workload)
     if not os.path.exists(p):
@@ -201,7 +237,10 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batched"])
+    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serving"])
+    ap.add_argument("--jobs", type=int, default=256)
+    ap.add_argument("--slots", type=int, default=32)
+    ap.add_argument("--budget-gib", type=float, default=96.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build proves one worker's share on a single MI355X "
@@ -211,6 +250,16 @@ def main():
     import torch
     from paper_2404_10404_amd import gkr
 
+    if args.mode == "serving":
+        res = serving_comparison(gkr, args.jobs, args.slots, args.budget_gib)
+        cb = res["continuous_batching"]
+        line = {"metric": "GKR serving: jobs/s and p50/p99 latency, continuous batching vs plain loop",
+                "value": cb["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+                "ms_per_step": round(cb["makespan_s"] * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": "u32 (BN254 Fr, exact modular integer arithmetic)",
+                "data": "synthetic", "config": {"workload": res["workload"]}, "serving": res}
+        print(json.dumps(line), flush=True)
+        return
     if args.mode == "batched":
         res = batched_comparison(gkr, args.steps, args.warmup)
         line = {"metric": "GKR prover field-gates/sec, batched persistent launch vs plain per-job launches",

@@ -97,6 +97,30 @@ def _less_than_modulus(w: Sequence[np.ndarray]) -> np.ndarray:
 def field_elements(key: int, count: int, start: int = 0) -> np.ndarray:
     """Uniform canonical field elements start..start+count-1 of the element stream `key`.
 
+    Large ranges are split into blocks generated on a thread pool (each element
+    depends only on its own index, so the split does not change the values).
+    """
+    block = 1 << 20
+    if count <= 2 * block:
+        return _field_elements_block(key, count, start)
+    import concurrent.futures
+    import os
+    out = np.empty((count, 8), dtype=np.uint32)
+    starts = list(range(0, count, block))
+    workers = max(1, min(16, os.cpu_count() or 1))
+
+    def fill(off):
+        n = min(block, count - off)
+        out[off:off + n] = _field_elements_block(key, n, start + off)
+
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        list(ex.map(fill, starts))
+    return out
+
+
+def _field_elements_block(key: int, count: int, start: int = 0) -> np.ndarray:
+    """Uniform canonical field elements start..start+count-1 of the element stream `key`.
+
     Element k draws its own sub-stream with state stream_at(key, k); attempt a
     takes that sub-stream's outputs 4a..4a+3 as little-endian 64-bit words,
     keeps the low 254 bits, and is accepted when the value is below the modulus

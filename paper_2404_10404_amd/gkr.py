@@ -83,8 +83,38 @@ def lib() -> ctypes.CDLL:
         L.gkr_prove_layer.restype = _i32
         L.gkr_verify.argtypes = [_vp, _vp, _vp, _u64, _vp, _sz]
         L.gkr_verify.restype = _i32
+        L.gkr_set_tuning.argtypes = [_u32, _u32]
+        L.gkr_set_tuning.restype = _i32
         _lib = L
+        _apply_tuning_cache(L)
     return _lib
+
+
+TUNING_CACHE = os.path.join(_HERE, "tuning.json")
+_tuned = {}
+
+
+def _apply_tuning_cache(L):
+    """Apply the autotuner's cached choice (paper_2404_10404_amd/autotune.py), if present."""
+    if not os.path.exists(TUNING_CACHE):
+        return
+    import json
+    with open(TUNING_CACHE) as f:
+        best = json.load(f).get("best", {})
+    if "tail_log" in best and "max_round_blocks" in best:
+        _check_with(L, L.gkr_set_tuning(int(best["tail_log"]), int(best["max_round_blocks"])))
+    _tuned.update(best)
+
+
+def _check_with(L, rc):
+    if rc < 0:
+        raise GkrError(rc, L.gkr_last_error().decode())
+
+
+def tuned_batch_workgroups() -> int:
+    """Resident workgroups of the batch kernel chosen by the autotuner (0 = fill the device)."""
+    lib()
+    return int(_tuned.get("batch_workgroups", 0))
 
 
 def _check(rc: int) -> int:
@@ -309,8 +339,11 @@ class Plan:
             pass
 
 
-def run_batch(plans: Sequence[Plan], d_ctl, workgroups: int = 0, step_budget: int = 0,
+def run_batch(plans: Sequence[Plan], d_ctl, workgroups: int = -1, step_budget: int = 0,
               stop_on_finish: bool = False, stream=None):
+    """gkr_run_batch; workgroups=-1 uses the autotuned count (0 = fill the device)."""
+    if workgroups < 0:
+        workgroups = tuned_batch_workgroups()
     arr = (_vp * len(plans))(*[p.handle.value for p in plans])
     _check(_batch_lib().gkr_run_batch(arr, len(plans), _ptr(d_ctl), workgroups, step_budget,
                                       1 if stop_on_finish else 0, _stream(stream)))

@@ -56,3 +56,12 @@ def test_workload_shapes():
         assert 12 <= j.log_width(0) <= 22 and 8 <= j.depth <= 24
     gaps = gs.poisson_gaps(10000, rate=4.0)
     assert abs(gaps.mean() - 0.25) < 0.02 and gaps.min() >= 0
+
+
+def test_threaded_generation_matches_blocks():
+    key = gs.stream_key(21, gs.PURPOSE_INPUT)
+    n = (1 << 21) + 777
+    full = gs.field_elements(key, n)  # threaded path
+    for off in (0, (1 << 20) - 5, (1 << 21) + 100):
+        cnt = min(4096, n - off)
+        assert np.array_equal(full[off:off + cnt], gs._field_elements_block(key, cnt, off))
