@@ -207,15 +207,21 @@ def serving_comparison(gkr, njobs, max_slots, budget_gib, util=0.8):
         t += float(g)
         r.arrival = t
     plain = serve.serve_plain(reqs, keep_proofs=True)
-    mixed = serve.serve(reqs, serve.GpuExecutor(keep_proofs=True), max_slots=max_slots,
-                        budget_bytes=int(budget_gib * (1 << 30)))
-    same = all(mixed[r.rid].proof == plain[r.rid].proof and mixed[r.rid].proof is not None for r in reqs)
+    budget = int(budget_gib * (1 << 30))
+    mixed = serve.serve(reqs, serve.StreamExecutor(keep_proofs=True), max_slots=max_slots, budget_bytes=budget)
     torch.cuda.synchronize()
+    persistent = serve.serve(reqs, serve.GpuExecutor(keep_proofs=True), max_slots=max_slots, budget_bytes=budget)
+    torch.cuda.synchronize()
+    same = all(mixed[r.rid].proof == plain[r.rid].proof == persistent[r.rid].proof and mixed[r.rid].proof is not None
+               for r in reqs)
     return {
         "workload": "%d jobs: log2 gates/layer uniform in [12,22], depth in [8,24], Poisson arrivals" % len(reqs),
         "arrival_rate_per_s": round(rate, 3), "mean_plain_service_s": round(mean_service, 5),
         "max_slots": max_slots, "hbm_budget_gib": budget_gib,
-        "plain_loop": serve.summary(plain, reqs), "continuous_batching": serve.summary(mixed, reqs),
+        "plain_loop": serve.summary(plain, reqs),
+        "continuous_batching": dict(serve.summary(mixed, reqs), executor="4 HIP streams, whole proofs enqueued"),
+        "continuous_batching_persistent": dict(serve.summary(persistent, reqs),
+                                               executor="persistent batch kernel, epochs end when a job finishes"),
         "proofs_identical_alone_and_in_mix": same,
     }
 

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgkr.so")
-SOURCES = ["gkr_kernels.hip", "gkr_api.hip", "gkr_tuning.cpp", "gkr_verify.cpp", "gkr_profile.cpp", "gkr_batch.hip"]
+SOURCES = ["gkr_batch_kernel.hip", "gkr_kernels.hip", "gkr_api.hip", "gkr_tuning.cpp", "gkr_verify.cpp", "gkr_profile.cpp", "gkr_batch.hip"]
 ARCH = "gfx950"
 
 # Packed fp32 instructions are switched off for every device compilation.

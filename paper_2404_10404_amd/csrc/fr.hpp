@@ -98,6 +98,7 @@ GKR_HD Fr fr_add(const Fr& a, const Fr& b) {
   return fr_reduce_once(s);
 }
 
+// a - b; p is added back under a mask (no branch) when the difference borrows.
 GKR_HD Fr fr_sub(const Fr& a, const Fr& b) {
   Fr d;
   uint64_t br = 0;
@@ -107,14 +108,13 @@ GKR_HD Fr fr_sub(const Fr& a, const Fr& b) {
     d.v[k] = (uint32_t)x;
     br = x >> 63;
   }
-  if (br) {
-    uint64_t c = 0;
+  const uint32_t mask = 0u - (uint32_t)br;
+  uint64_t c = 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      uint64_t x = (uint64_t)d.v[k] + p_limb(k) + c;
-      d.v[k] = (uint32_t)x;
-      c = x >> 32;
-    }
+  for (int k = 0; k < 8; ++k) {
+    uint64_t x = (uint64_t)d.v[k] + (p_limb(k) & mask) + c;
+    d.v[k] = (uint32_t)x;
+    c = x >> 32;
   }
   return d;
 }
@@ -174,7 +174,97 @@ __device__ __forceinline__ Fr fr_mul_device(const Fr& a, const Fr& b) {
   r.v[7] = (uint32_t)acc;
   return fr_reduce_once(r);
 }
+#else
+// Host form of the column multiply-accumulate: (ov:acc) += x * y.
+GKR_HD void fr_mac_vv(uint64_t& acc, uint32_t& ov, uint32_t x, uint32_t y) {
+  const uint64_t s = acc + (uint64_t)x * y;
+  ov += (s < acc) ? 1u : 0u;
+  acc = s;
+}
+GKR_HD void fr_mac_vs(uint64_t& acc, uint32_t& ov, uint32_t x, uint32_t y) { fr_mac_vv(acc, ov, x, y); }
 #endif
+
+// Unreduced (lazy) products: a 512-bit accumulator of sums of products of
+// reduced values, reduced once at the end. A product into the accumulator
+// costs 64 multiply-adds instead of the 136 of a Montgomery product, so sums
+// of products (dot products, a*b + c*d) pay for one reduction only.
+struct FrWide {
+  uint32_t w[16];
+};
+
+GKR_HD FrWide frw_zero() {
+  FrWide A;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) A.w[k] = 0;
+  return A;
+}
+
+// A += a * b by product scanning. The carry between columns is below 2^35,
+// so adding the accumulator's word to it cannot overflow 64 bits.
+GKR_HD void frw_mac(FrWide& A, const Fr& a, const Fr& b) {
+  uint64_t acc = 0;
+  uint32_t ov = 0;
+#pragma unroll
+  for (int k = 0; k < 15; ++k) {
+    acc += A.w[k];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int j = k - i;
+      if (j >= 0 && j < 8) fr_mac_vv(acc, ov, a.v[i], b.v[j]);
+    }
+    A.w[k] = (uint32_t)acc;
+    acc = (acc >> 32) | ((uint64_t)ov << 32);
+    ov = 0;
+  }
+  A.w[15] += (uint32_t)acc;
+}
+
+// Montgomery reduction of an accumulator of at most `Terms` products of
+// reduced values: returns A * R^{-1} mod p, reduced. With p/2^256 < 0.1895,
+// A < Terms * p^2 gives a high half below 0.1895 * Terms * p; subtracting p
+// from it until it is below p changes A by multiples of pR only, after which
+// A < pR and the reduction of the low words leaves a value below 2p.
+template <int Terms>
+GKR_HD Fr frw_reduce(const FrWide& A) {
+  static_assert(Terms >= 1 && Terms <= 16, "accumulator bound");
+  constexpr int kSub = Terms <= 5 ? 0 : Terms <= 10 ? 1 : Terms <= 15 ? 2 : 3;
+  Fr hi;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) hi.v[k] = A.w[8 + k];
+#pragma unroll
+  for (int rep = 0; rep < kSub; ++rep) hi = fr_reduce_once(hi);
+  uint32_t m[8];
+  Fr r;
+  uint64_t acc = 0;
+  uint32_t ov = 0;
+#pragma unroll
+  for (int k = 0; k < 15; ++k) {
+    acc += k < 8 ? A.w[k] : hi.v[k - 8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = k - j;
+      if (j < k && i >= 1 && i < 8) fr_mac_vs(acc, ov, m[j], p_limb(i));
+    }
+    if (k < 8) {
+      m[k] = (uint32_t)acc * GKR_NINV;
+      fr_mac_vs(acc, ov, m[k], GKR_P0);
+    } else {
+      r.v[k - 8] = (uint32_t)acc;
+    }
+    acc = (acc >> 32) | ((uint64_t)ov << 32);
+    ov = 0;
+  }
+  r.v[7] = (uint32_t)acc + hi.v[7];
+  return fr_reduce_once(r);
+}
+
+// a*b + c*d with one reduction.
+GKR_HD Fr fr_mul_add2(const Fr& a, const Fr& b, const Fr& c, const Fr& d) {
+  FrWide A = frw_zero();
+  frw_mac(A, a, b);
+  frw_mac(A, c, d);
+  return frw_reduce<2>(A);
+}
 
 // Montgomery product a*b*R^{-1} mod p. Host: coarsely integrated operand
 // scanning (CIOS) in plain C; device: the product-scanning form above.

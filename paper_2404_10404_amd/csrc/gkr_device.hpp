@@ -9,16 +9,22 @@
 
 namespace gkr {
 
+// Table elements live in device (global) memory: the loads and stores go
+// through address-space-1 pointers so that they compile to global (not flat)
+// memory instructions.
+typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) U32x4 GlobalU4;
+
 __device__ __forceinline__ Fr ldf(const Fr* p, uint64_t i) {
-  const uint4* q = reinterpret_cast<const uint4*>(p + i);
-  uint4 a = q[0], b = q[1];
+  const GlobalU4* q = (const GlobalU4*)(p + i);
+  const U32x4 a = q[0], b = q[1];
   return fr_make(a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w);
 }
 
 __device__ __forceinline__ void stf(Fr* p, uint64_t i, const Fr& v) {
-  uint4* q = reinterpret_cast<uint4*>(p + i);
-  q[0] = make_uint4(v.v[0], v.v[1], v.v[2], v.v[3]);
-  q[1] = make_uint4(v.v[4], v.v[5], v.v[6], v.v[7]);
+  GlobalU4* q = (GlobalU4*)(p + i);
+  q[0] = U32x4{v.v[0], v.v[1], v.v[2], v.v[3]};
+  q[1] = U32x4{v.v[4], v.v[5], v.v[6], v.v[7]};
 }
 
 __device__ __forceinline__ Fr shfl_xor_fr(const Fr& a, int mask) {

@@ -1,819 +1,9 @@
-// HIP kernels of the data-parallel GKR prover for gfx950.
-//
-// Every kernel uses 256-thread workgroups (four 64-wide waves). Field elements
-// are 32-byte records in Montgomery form, loaded and stored as two 16-byte
-// vectors, so consecutive threads touch consecutive records and every access
-// of a table sweep is coalesced. Gate g = z*2^n + c keeps the copy index in the
-// low bits: a gather W[(y_z << n) | c] over consecutive c is contiguous.
-//
-// Each kernel is a step body over (tile, ntiles): tile plays the role of the
-// workgroup index and ntiles of the grid size. The plain path launches one
-// kernel per step with grid = ntiles; the persistent batch kernel
-// (gkr_batch.hip) hands tiles of many proofs' steps to resident workgroups.
-//
-// Reductions over a whole table (the round polynomials of the sumcheck) end in
-// the last tile to finish: each tile writes its partial sums, publishes them
-// with a device-scope fence and an atomic counter, and the tile that brings the
-// counter to ntiles adds the partials and runs the Fiat-Shamir step (absorb
-// the message, take the challenge, move the claim) in its first wave.
-// Challenges and claims never leave device memory, so a proof is a plain
-// sequence of launches on one stream.
-#include "gkr_device.hpp"
-#include "gkr_kernels.hpp"
+// Plain kernels of the GKR prover for gfx950: one kernel per step type,
+// launched with grid = the step's tile count (the bodies are in gkr_bodies.hpp).
+#include "gkr_bodies.hpp"
 #include "gkr_profile.hpp"
 
 namespace gkr {
-
-// ---------------------------------------------------------- transcript
-
-// SHA-256 of a fixed-length word message (big-endian words).
-template <int L>
-__device__ __forceinline__ Sha256State sha256_fixed(const uint32_t* w) {
-  constexpr int B = (L + 3 + 15) / 16;
-  Sha256State st = sha256_iv();
-#pragma unroll
-  for (int b = 0; b < B; ++b) {
-    Sha256Block blk;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int idx = b * 16 + i;
-      uint32_t v;
-      if (idx < L) v = w[idx];
-      else if (idx == L) v = 0x80000000u;
-      else if (idx == B * 16 - 1) v = (uint32_t)(L * 32);
-      else v = 0u;
-      blk.w[i] = v;
-    }
-    st = sha256_compress_v(st, blk);
-  }
-  return st;
-}
-
-__device__ __forceinline__ Sha256State load_state(const DevState* S) {
-  Sha256State s;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) s.h[k] = S->st[k];
-  return s;
-}
-
-__device__ __forceinline__ void save_state(DevState* S, const Sha256State& s) {
-#pragma unroll
-  for (int k = 0; k < 8; ++k) S->st[k] = s.h[k];
-}
-
-// The current state as a challenge: rehash with "GKRC" until the 254-bit
-// little-endian value is below p. Each attempt is accepted with probability
-// p / 2^254 > 3/4; the bound on attempts only guarantees termination.
-__device__ Fr accept(Sha256State& st) {
-  Fr c = sha256_to_candidate(st);
-  for (int attempt = 0; attempt < 4096 && !fr_is_canonical(c); ++attempt) {
-    uint32_t w[9];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) w[k] = st.h[k];
-    w[8] = kTagChallenge;
-    st = sha256_fixed<9>(w);
-    c = sha256_to_candidate(st);
-  }
-  return c;
-}
-
-__device__ Fr squeeze(Sha256State& st) {
-  uint32_t w[9];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) w[k] = st.h[k];
-  w[8] = kTagChallenge;
-  st = sha256_fixed<9>(w);
-  return accept(st);
-}
-
-__device__ void absorb_element(Sha256State& st, uint32_t tag, const Fr& canonical) {
-  uint32_t w[17];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) w[k] = st.h[k];
-  w[8] = tag;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) w[9 + k] = bswap32(canonical.v[k]);
-  st = sha256_fixed<17>(w);
-}
-
-__device__ void absorb_digest(Sha256State& st, const uint32_t* d) {
-  uint32_t w[17];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) w[k] = st.h[k];
-  w[8] = kTagDigest;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) w[9 + k] = d[k];
-  st = sha256_fixed<17>(w);
-}
-
-__device__ __forceinline__ Fr fr_one_canonical() { return fr_make(1, 0, 0, 0, 0, 0, 0, 0); }
-
-// Round message (e0, e1 = claim - e0, e2), run by all 64 lanes of one wave
-// with e0, e2 the same in every lane: write the message to the proof, absorb
-// (e0, e2), take the challenge r, store r and move the claim to
-// g(r) = e0 + r (e1 - e0) + r (r - 1) (e2 - 2 e1 + e0) / 2.
-// Independent products run in different lanes: 4 products on the serial path.
-__device__ void finish_round_wave(DevState* S, const Fr& e0, const Fr& e2, Fr* r_out,
-                                  uint32_t* msg_out) {
-  const int lane = threadIdx.x & 63;
-  const Fr claim = S->claim;
-  const Fr e1 = fr_sub(claim, e0);
-  const Fr d1 = fr_sub(e1, e0);
-  const Fr d2 = fr_add(fr_sub(e2, fr_double(e1)), e0);
-  // lanes 0, 1, 2: canonical e0, canonical e2, d2 / 2
-  Fr a = lane == 0 ? e0 : (lane == 1 ? e2 : d2);
-  Fr b = lane < 2 ? fr_one_canonical() : fr_inv2();
-  Fr prod = fr_mul(a, b);
-  const Fr c0 = shfl_fr(prod, 0), c2 = shfl_fr(prod, 1), d2h = shfl_fr(prod, 2);
-  uint32_t w[25];
-  Sha256State st = load_state(S);
-#pragma unroll
-  for (int k = 0; k < 8; ++k) w[k] = st.h[k];
-  w[8] = kTagRound;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    w[9 + k] = bswap32(c0.v[k]);
-    w[17 + k] = bswap32(c2.v[k]);
-  }
-  st = sha256_fixed<25>(w);
-  const Fr r = fr_mul(accept(st), fr_r2());
-  if (lane == 0) {
-    stf(r_out, 0, r);
-    save_state(S, st);
-  }
-  // lanes 0, 1, 2: r d1, r (r - 1), canonical e1
-  a = lane == 2 ? e1 : r;
-  b = lane == 0 ? d1 : (lane == 1 ? fr_sub(r, fr_one()) : fr_one_canonical());
-  prod = fr_mul(a, b);
-  const Fr rd1 = shfl_fr(prod, 0), rr = shfl_fr(prod, 1), c1 = shfl_fr(prod, 2);
-  const Fr quad = fr_mul(rr, d2h);
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      msg_out[k] = c0.v[k];
-      msg_out[8 + k] = c1.v[k];
-      msg_out[16 + k] = c2.v[k];
-    }
-    S->claim = fr_add(fr_add(e0, rd1), quad);
-  }
-}
-
-// A phase's final value (one thread): store it, write it to the proof and absorb it.
-__device__ void finish_value(DevState* S, const Fr& v, Fr* v_out, uint32_t* proof_out) {
-  const Fr c = fr_from_mont(v);
-  Sha256State st = load_state(S);
-  absorb_element(st, kTagValue, c);
-  save_state(S, st);
-  *v_out = v;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) proof_out[k] = c.v[k];
-}
-
-// ---------------------------------------------------------------- bodies
-
-#define GTID ((uint64_t)tile * kBlock + threadIdx.x)
-#define GSTRIDE ((uint64_t)ntiles * kBlock)
-
-// ST_TO_MONT: p0 canonical in, p1 out, q0 count.
-__device__ void body_to_mont(const Step& st, uint32_t tile, uint32_t ntiles) {
-  const Fr* in = P<const Fr*>(st, 0);
-  Fr* out = P<Fr*>(st, 1);
-  for (uint64_t i = GTID; i < st.q[0]; i += GSTRIDE) stf(out, i, fr_to_mont(ldf(in, i)));
-}
-
-// ST_FROM_MONT: p0 in, p1 canonical out, q0 count.
-__device__ void body_from_mont(const Step& st, uint32_t tile, uint32_t ntiles) {
-  const Fr* in = P<const Fr*>(st, 0);
-  Fr* out = P<Fr*>(st, 1);
-  for (uint64_t i = GTID; i < st.q[0]; i += GSTRIDE) stf(out, i, fr_from_mont(ldf(in, i)));
-}
-
-// ST_FORWARD: V_i[z*2^n + c] = W[x_z*2^n + c] (+ or *) W[y_z*2^n + c].
-// p0 W, p1 V, p2 gate records, u0 n, q0 count.
-__device__ void body_forward(const Step& st, uint32_t tile, uint32_t ntiles) {
-  const Fr* __restrict__ W = P<const Fr*>(st, 0);
-  Fr* __restrict__ V = P<Fr*>(st, 1);
-  const uint2* __restrict__ gates = P<const uint2*>(st, 2);
-  const uint32_t n = st.u[0];
-  const uint64_t mask = (1ull << n) - 1;
-  for (uint64_t g = GTID; g < st.q[0]; g += GSTRIDE) {
-    const uint64_t z = g >> n, c = g & mask;
-    const uint2 gate = gates[z];
-    const uint64_t x = gate.x & 0x7fffffffu, y = gate.y;
-    const Fr a = ldf(W, (x << n) | c), b = ldf(W, (y << n) | c);
-    stf(V, g, (gate.x >> 31) ? fr_mul(a, b) : fr_add(a, b));
-  }
-}
-
-// ST_DIGEST: one level of a tree digest; chunk t of q0 words (256 words, 1 KiB,
-// per chunk) is hashed by thread t; element words are byte-swapped (limbs are
-// little-endian). p0 in, p1 out, q0 nwords, q1 nchunks, u0 swap.
-__device__ void body_digest(const Step& st, uint32_t tile, uint32_t ntiles) {
-  const uint32_t* __restrict__ in = P<const uint32_t*>(st, 0);
-  uint32_t* __restrict__ out = P<uint32_t*>(st, 1);
-  const uint64_t nwords = st.q[0];
-  const int swap = st.u[0];
-  for (uint64_t t = GTID; t < st.q[1]; t += GSTRIDE) {
-    const uint64_t begin = t * kChunkWords;
-    const uint64_t end = (begin + kChunkWords < nwords) ? begin + kChunkWords : nwords;
-    const uint64_t len = end - begin;  // a multiple of 8 words
-    Sha256State sh = sha256_iv();
-    const uint4* src = reinterpret_cast<const uint4*>(in + begin);
-    const uint64_t full = len / 16;
-    for (uint64_t b = 0; b < full; ++b) {
-      Sha256Block blk;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint4 v = src[b * 4 + q];
-        blk.w[4 * q + 0] = swap ? bswap32(v.x) : v.x;
-        blk.w[4 * q + 1] = swap ? bswap32(v.y) : v.y;
-        blk.w[4 * q + 2] = swap ? bswap32(v.z) : v.z;
-        blk.w[4 * q + 3] = swap ? bswap32(v.w) : v.w;
-      }
-      sh = sha256_compress_v(sh, blk);
-    }
-    Sha256Block blk;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) blk.w[i] = 0;
-    if (len - full * 16 == 8) {
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const uint4 v = src[full * 4 + q];
-        blk.w[4 * q + 0] = swap ? bswap32(v.x) : v.x;
-        blk.w[4 * q + 1] = swap ? bswap32(v.y) : v.y;
-        blk.w[4 * q + 2] = swap ? bswap32(v.z) : v.z;
-        blk.w[4 * q + 3] = swap ? bswap32(v.w) : v.w;
-      }
-      blk.w[8] = 0x80000000u;
-    } else {
-      blk.w[0] = 0x80000000u;
-    }
-    const uint64_t bits = len * 32;
-    blk.w[14] = (uint32_t)(bits >> 32);
-    blk.w[15] = (uint32_t)bits;
-    sh = sha256_compress_v(sh, blk);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) out[t * 8 + k] = sh.h[k];
-  }
-}
-
-// ST_TRANSCRIPT_BEGIN: st = seed state (w0..7), then absorb the circuit digest
-// (w8..15) and the two vector digests; also zeroes the reduction counter.
-// p0 S, p1 dig_in, p2 dig_out.
-__device__ void body_transcript_begin(const Step& st, uint32_t, uint32_t) {
-  if (threadIdx.x != 0) return;
-  DevState* S = P<DevState*>(st, 0);
-  Sha256State sh;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) sh.h[k] = st.w[k];
-  absorb_digest(sh, st.w + 8);
-  absorb_digest(sh, P<const uint32_t*>(st, 1));
-  absorb_digest(sh, P<const uint32_t*>(st, 2));
-  save_state(S, sh);
-  S->counter = 0;
-}
-
-// ST_SQUEEZE: u0 challenges into p1 (Montgomery form). p0 S.
-__device__ void body_squeeze(const Step& st, uint32_t, uint32_t) {
-  if (threadIdx.x != 0) return;
-  DevState* S = P<DevState*>(st, 0);
-  Fr* out = P<Fr*>(st, 1);
-  Sha256State sh = load_state(S);
-  for (uint32_t k = 0; k < st.u[0]; ++k) stf(out, k, fr_to_mont(squeeze(sh)));
-  save_state(S, sh);
-}
-
-// ST_LAYER_BEGIN: draw alpha, beta (layer > 0) and set the claim to
-// alpha * vu + beta * vv; on layer 0 (u0 = 1) alpha = 1, beta = 0 and claim = vu.
-// p0 S, p1 vu, p2 vv.
-__device__ void body_layer_begin(const Step& st, uint32_t, uint32_t) {
-  if (threadIdx.x != 0) return;
-  DevState* S = P<DevState*>(st, 0);
-  const Fr vu = *P<const Fr*>(st, 1), vv = *P<const Fr*>(st, 2);
-  if (st.u[0]) {
-    S->alpha = fr_one();
-    S->beta = fr_zero();
-    S->claim = vu;
-    return;
-  }
-  Sha256State sh = load_state(S);
-  const Fr a = fr_to_mont(squeeze(sh));
-  const Fr b = fr_to_mont(squeeze(sh));
-  save_state(S, sh);
-  S->alpha = a;
-  S->beta = b;
-  S->claim = fr_add(fr_mul(a, vu), fr_mul(b, vv));
-}
-
-// ST_EQ: up to four tables out_j[b] = scale_j * prod_k (bit_k(b) ? r_k : 1 - r_k),
-// bit 1 = MSB. u0..3 bits, u4 count; p0..3 points, p4..7 scales (null = 1), p8..11 outs.
-__device__ void body_eq(const Step& st, uint32_t tile, uint32_t ntiles) {
-  uint64_t total = 0;
-  for (uint32_t j = 0; j < st.u[4]; ++j) total += 1ull << st.u[j];
-  for (uint64_t g = GTID; g < total; g += GSTRIDE) {
-    uint64_t t = g;
-    uint32_t j = 0;
-    while (t >= (1ull << st.u[j])) {
-      t -= 1ull << st.u[j];
-      ++j;
-    }
-    const Fr* r = P<const Fr*>(st, j);
-    const int k = st.u[j];
-    const Fr* scale = P<const Fr*>(st, 4 + j);
-    Fr acc = scale ? *scale : fr_one();
-    for (int i = 0; i < k; ++i) {
-      const Fr ri = ldf(r, i);
-      const bool bit = (t >> (k - 1 - i)) & 1;
-      acc = fr_mul(acc, bit ? ri : fr_one_minus(ri));
-    }
-    stf(P<Fr*>(st, 8 + j), t, acc);
-  }
-}
-
-// ST_WSUM: sum_e V[e] A[e >> n] B[e & mask] into *p5.
-// p0 V, p1 A, p2 B, p3 partials, p4 S, p5 dst, u0 n, q0 count.
-__device__ void body_wsum(const Step& st, uint32_t tile, uint32_t ntiles) {
-  const Fr* V = P<const Fr*>(st, 0);
-  const Fr* A = P<const Fr*>(st, 1);
-  const Fr* B = P<const Fr*>(st, 2);
-  const uint32_t n = st.u[0];
-  const uint64_t mask = (1ull << n) - 1;
-  Fr acc[1] = {fr_zero()};
-  for (uint64_t e = GTID; e < st.q[0]; e += GSTRIDE)
-    acc[0] = fr_add(acc[0], fr_mul(fr_mul(ldf(V, e), ldf(A, e >> n)), ldf(B, e & mask)));
-  write_partial<1>(acc, P<Fr*>(st, 3), tile);
-}
-__device__ void finish_wsum(const Step& st, uint32_t ntiles) {
-  Fr tot[1];
-  sum_partials<1>(P<const Fr*>(st, 3), ntiles, tot);
-  if (threadIdx.x == 0) *P<Fr*>(st, 5) = tot[0];
-}
-
-// Phase-1 bookkeeping tables over (x, c):
-//   G[x,c] = sum_{MUL z: x_z=x} T[z,c] W[y_z,c] + sum_{ADD z: x_z=x} T[z,c]
-//   H[x,c] = sum_{ADD z: x_z=x} T[z,c] W[y_z,c]
-// with T[z,c] = aU[z] Cu[c] + bV[z] Cv[c] (the factored eq of both claims).
-// p0 W, p1 G, p2 H, p3 xrow, p4 xent, p5 aU, p6 bV, p7 Cu, p8 Cv, u0 n.
-__device__ __forceinline__ void phase1_entry(const Step& st, uint64_t e, Fr& g, Fr& h) {
-  const Fr* __restrict__ W = P<const Fr*>(st, 0);
-  const uint32_t* __restrict__ xrow = P<const uint32_t*>(st, 3);
-  const uint2* __restrict__ xent = P<const uint2*>(st, 4);
-  const Fr* __restrict__ aU = P<const Fr*>(st, 5);
-  const Fr* __restrict__ bV = P<const Fr*>(st, 6);
-  const uint32_t n = st.u[0];
-  const uint64_t mask = (1ull << n) - 1;
-  const uint64_t x = e >> n, c = e & mask;
-  const Fr cu = ldf(P<const Fr*>(st, 7), c), cv = ldf(P<const Fr*>(st, 8), c);
-  g = fr_zero();
-  h = fr_zero();
-  const uint32_t k1 = xrow[x + 1];
-  for (uint32_t k = xrow[x]; k < k1; ++k) {
-    const uint2 ent = xent[k];
-    const uint64_t z = ent.x, y = ent.y & 0x7fffffffu;
-    const Fr T = fr_add(fr_mul(ldf(aU, z), cu), fr_mul(ldf(bV, z), cv));
-    const Fr tw = fr_mul(T, ldf(W, (y << n) | c));
-    if (ent.y >> 31) {
-      g = fr_add(g, tw);
-    } else {
-      g = fr_add(g, T);
-      h = fr_add(h, tw);
-    }
-  }
-}
-
-// ST_P1_INIT: the tables alone; q0 count.
-__device__ void body_p1_init(const Step& st, uint32_t tile, uint32_t ntiles) {
-  Fr* G = P<Fr*>(st, 1);
-  Fr* H = P<Fr*>(st, 2);
-  for (uint64_t e = GTID; e < st.q[0]; e += GSTRIDE) {
-    Fr g, h;
-    phase1_entry(st, e, g, h);
-    stf(G, e, g);
-    stf(H, e, h);
-  }
-}
-
-// ST_P1_INIT_ROUND: the tables and the first round together: b builds entries
-// b and b + half and evaluates the round-1 pair at t = 0, 2.
-// q0 half; p9 S, p10 partials, p11 r_out, p12 msg.
-__device__ void body_p1_init_round(const Step& st, uint32_t tile, uint32_t ntiles) {
-  const Fr* W = P<const Fr*>(st, 0);
-  Fr* G = P<Fr*>(st, 1);
-  Fr* H = P<Fr*>(st, 2);
-  const uint64_t half = st.q[0];
-  Fr acc[2] = {fr_zero(), fr_zero()};
-  for (uint64_t b = GTID; b < half; b += GSTRIDE) {
-    Fr g0, h0, g1, h1;
-    phase1_entry(st, b, g0, h0);
-    phase1_entry(st, b + half, g1, h1);
-    stf(G, b, g0);
-    stf(H, b, h0);
-    stf(G, b + half, g1);
-    stf(H, b + half, h1);
-    const Fr w0 = ldf(W, b), w1 = ldf(W, b + half);
-    acc[0] = fr_add(acc[0], fr_add(fr_mul(w0, g0), h0));
-    const Fr w2 = fr_sub(fr_double(w1), w0), g2 = fr_sub(fr_double(g1), g0), h2 = fr_sub(fr_double(h1), h0);
-    acc[1] = fr_add(acc[1], fr_add(fr_mul(w2, g2), h2));
-  }
-  write_partial<2>(acc, P<Fr*>(st, 10), tile);
-}
-
-// Sum of the partials, then the Fiat-Shamir step in wave 0.
-__device__ void finish_reduced_round(const Fr* partials, uint32_t ntiles, DevState* S, Fr* r_out,
-                                     uint32_t* msg) {
-  Fr tot[2];
-  sum_partials<2>(partials, ntiles, tot);
-  broadcast_from_thread0<2>(tot);
-  if (threadIdx.x < 64) finish_round_wave(S, tot[0], tot[1], r_out, msg);
-}
-
-__device__ void finish_p1_init_round(const Step& st, uint32_t ntiles) {
-  finish_reduced_round(P<const Fr*>(st, 10), ntiles, P<DevState*>(st, 9), P<Fr*>(st, 11), P<uint32_t*>(st, 12));
-}
-
-// Fold (if `fold`) and evaluate one pair b of a round: the evaluated table has
-// 2*half entries; with folding the source has 4*half entries and the folded
-// entries b and b + half are written to dst.
-template <class Form>
-__device__ __forceinline__ void round_pair(const Fr* const* src, Fr* const* dst, uint64_t b,
-                                           uint64_t half, bool fold, const Fr& r, Fr& acc0,
-                                           Fr& acc2) {
-  Fr x0[Form::NT], x2[Form::NT];
-#pragma unroll
-  for (int k = 0; k < Form::NT; ++k) {
-    Fr lo, hi;
-    if (fold) {
-      const uint64_t m = 2 * half;
-      const Fr a0 = ldf(src[k], b), a1 = ldf(src[k], b + m);
-      const Fr b0 = ldf(src[k], b + half), b1 = ldf(src[k], b + half + m);
-      lo = fr_add(a0, fr_mul(r, fr_sub(a1, a0)));
-      hi = fr_add(b0, fr_mul(r, fr_sub(b1, b0)));
-      stf(dst[k], b, lo);
-      stf(dst[k], b + half, hi);
-    } else {
-      lo = ldf(src[k], b);
-      hi = ldf(src[k], b + half);
-    }
-    x0[k] = lo;
-    x2[k] = fr_sub(fr_double(hi), lo);  // value at t = 2
-  }
-  Form::eval(x0, acc0);
-  Form::eval(x2, acc2);
-}
-
-// ST_ROUND_A / ST_ROUND_B: one sumcheck round (optional fold by the previous
-// challenge, evaluation at t = 0, 2); q0 half. Pointers: src[0..NT),
-// dst[NT..2NT), then rprev, S, partials, r_out, msg (RoundPtrs).
-template <class Form>
-__device__ void body_round(const Step& st, uint32_t tile, uint32_t ntiles) {
-  using R = RoundPtrs<Form::NT>;
-  const Fr* src[Form::NT];
-  Fr* dst[Form::NT];
-#pragma unroll
-  for (int k = 0; k < Form::NT; ++k) {
-    src[k] = P<const Fr*>(st, k);
-    dst[k] = P<Fr*>(st, Form::NT + k);
-  }
-  const Fr* rprev = P<const Fr*>(st, R::kR);
-  const bool fold = rprev != nullptr;
-  const Fr r = fold ? ldf(rprev, 0) : fr_zero();
-  const uint64_t half = st.q[0];
-  Fr acc[2] = {fr_zero(), fr_zero()};
-  for (uint64_t b = GTID; b < half; b += GSTRIDE) round_pair<Form>(src, dst, b, half, fold, r, acc[0], acc[1]);
-  write_partial<2>(acc, P<Fr*>(st, R::kPart), tile);
-}
-template <class Form>
-__device__ void finish_round_step(const Step& st, uint32_t ntiles) {
-  using R = RoundPtrs<Form::NT>;
-  finish_reduced_round(P<const Fr*>(st, R::kPart), ntiles, P<DevState*>(st, R::kS), P<Fr*>(st, R::kROut),
-                       P<uint32_t*>(st, R::kMsg));
-}
-
-// ST_TAIL_A / ST_TAIL_B: the remaining u0 rounds of a phase in one workgroup,
-// then the final fold. q0 = table size before the pending fold (if any).
-// Pointers: src, dst, rpending, S, r_out, msg, final_out, proof_value. The
-// final value of table 0 is stored in *final_out and, if proof_value is not
-// null, written to the proof and absorbed.
-template <class Form>
-__device__ void body_tail(const Step& st, uint32_t, uint32_t) {
-  constexpr int NT = Form::NT;
-  const Fr* src[NT];
-  Fr* dst[NT];
-#pragma unroll
-  for (int k = 0; k < NT; ++k) {
-    src[k] = P<const Fr*>(st, k);
-    dst[k] = P<Fr*>(st, NT + k);
-  }
-  const Fr* rpending = P<const Fr*>(st, 2 * NT);
-  DevState* S = P<DevState*>(st, 2 * NT + 1);
-  Fr* r_out = P<Fr*>(st, 2 * NT + 2);
-  uint32_t* msg = P<uint32_t*>(st, 2 * NT + 3);
-  Fr* final_out = P<Fr*>(st, 2 * NT + 4);
-  uint32_t* proof_value = P<uint32_t*>(st, 2 * NT + 5);
-  uint64_t size = st.q[0];
-  const uint32_t rounds = st.u[0];
-  __shared__ Fr r_sh;
-  bool fold = rpending != nullptr;
-  __syncthreads();
-  if (threadIdx.x == 0) r_sh = fold ? ldf(rpending, 0) : fr_zero();
-  __syncthreads();
-  for (uint32_t j = 0; j < rounds; ++j) {
-    const uint64_t eval_size = fold ? size / 2 : size;
-    const uint64_t half = eval_size / 2;
-    const Fr r = r_sh;
-    Fr acc[2] = {fr_zero(), fr_zero()};
-    for (uint64_t b = threadIdx.x; b < half; b += kBlock) round_pair<Form>(src, dst, b, half, fold, r, acc[0], acc[1]);
-    block_reduce<2>(acc);
-    broadcast_from_thread0<2>(acc);
-    if (threadIdx.x < 64) {
-      finish_round_wave(S, acc[0], acc[1], r_out + j, msg + 24 * j);
-      if (threadIdx.x == 0) r_sh = ldf(r_out + j, 0);
-    }
-    __syncthreads();
-    if (fold) {
-#pragma unroll
-      for (int k = 0; k < NT; ++k) src[k] = dst[k];
-    }
-    fold = true;
-    size = eval_size;
-  }
-  if (fold) {  // size is 2 here
-    if (threadIdx.x < NT) {
-      const int k = threadIdx.x;
-      const Fr r = r_sh;
-      const Fr a0 = ldf(src[k], 0), a1 = ldf(src[k], 1);
-      stf(dst[k], 0, fr_add(a0, fr_mul(r, fr_sub(a1, a0))));
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const Fr v = ldf(fold ? dst[0] : src[0], 0);
-    if (proof_value) finish_value(S, v, final_out, proof_value);
-    else *final_out = v;
-  }
-}
-
-// ST_COPY_WEIGHTS: U[c] = Cu[c] EC[c], V[c] = Cv[c] EC[c]; SU, SV their sums
-// (one workgroup). p0 Cu, p1 Cv, p2 EC, p3 U, p4 V, p5 S, q0 ncop.
-__device__ void body_copy_weights(const Step& st, uint32_t, uint32_t) {
-  const Fr* Cu = P<const Fr*>(st, 0);
-  const Fr* Cv = P<const Fr*>(st, 1);
-  const Fr* EC = P<const Fr*>(st, 2);
-  Fr* U = P<Fr*>(st, 3);
-  Fr* V = P<Fr*>(st, 4);
-  DevState* S = P<DevState*>(st, 5);
-  Fr acc[2] = {fr_zero(), fr_zero()};
-  for (uint64_t c = threadIdx.x; c < st.q[0]; c += kBlock) {
-    const Fr ec = ldf(EC, c);
-    const Fr u = fr_mul(ldf(Cu, c), ec), v = fr_mul(ldf(Cv, c), ec);
-    stf(U, c, u);
-    stf(V, c, v);
-    acc[0] = fr_add(acc[0], u);
-    acc[1] = fr_add(acc[1], v);
-  }
-  block_reduce<2>(acc);
-  if (threadIdx.x == 0) {
-    S->su = acc[0];
-    S->sv = acc[1];
-  }
-}
-
-// ST_P2_TABLES: phase-2 sub-circuit tables over y, the copy factors kept apart:
-//   M[y,c] = U[c] Ma[y] + V[c] Mb[y],  A[y,c] = U[c] Aa[y] + V[c] Ab[y]
-//   Ma[y] = sum_{MUL z: y_z=y} aU[z] EL[x_z] (Mb with bV; Aa, Ab over ADD gates)
-//   Fa = vx Ma + Aa, Fb = vx Mb + Ab, Ka = vx Aa, Kb = vx Ab, Ks = SU Ka + SV Kb.
-// p0 yrow, p1 yent, p2 aU, p3 bV, p4 EL, p5 S, p6 Fa, p7 Fb, p8 Ka, p9 Kb, p10 Ks, q0 count.
-__device__ void body_p2_tables(const Step& st, uint32_t tile, uint32_t ntiles) {
-  const uint32_t* __restrict__ yrow = P<const uint32_t*>(st, 0);
-  const uint2* __restrict__ yent = P<const uint2*>(st, 1);
-  const Fr* __restrict__ aU = P<const Fr*>(st, 2);
-  const Fr* __restrict__ bV = P<const Fr*>(st, 3);
-  const Fr* __restrict__ EL = P<const Fr*>(st, 4);
-  const DevState* S = P<const DevState*>(st, 5);
-  const Fr vx = S->vx, su = S->su, sv = S->sv;
-  for (uint64_t y = GTID; y < st.q[0]; y += GSTRIDE) {
-    Fr ma = fr_zero(), mb = fr_zero(), aa = fr_zero(), ab = fr_zero();
-    const uint32_t k1 = yrow[y + 1];
-    for (uint32_t k = yrow[y]; k < k1; ++k) {
-      const uint2 ent = yent[k];
-      const uint64_t z = ent.x, x = ent.y & 0x7fffffffu;
-      const Fr el = ldf(EL, x);
-      const Fr a = fr_mul(ldf(aU, z), el), b = fr_mul(ldf(bV, z), el);
-      if (ent.y >> 31) {
-        ma = fr_add(ma, a);
-        mb = fr_add(mb, b);
-      } else {
-        aa = fr_add(aa, a);
-        ab = fr_add(ab, b);
-      }
-    }
-    const Fr ka = fr_mul(vx, aa), kb = fr_mul(vx, ab);
-    stf(P<Fr*>(st, 6), y, fr_add(fr_mul(vx, ma), aa));
-    stf(P<Fr*>(st, 7), y, fr_add(fr_mul(vx, mb), ab));
-    stf(P<Fr*>(st, 8), y, ka);
-    stf(P<Fr*>(st, 9), y, kb);
-    stf(P<Fr*>(st, 10), y, fr_add(fr_mul(su, ka), fr_mul(sv, kb)));
-  }
-}
-
-// ST_COPY_CONTRACT: row sums over the copies, P[y] = sum_c U[c] W[y,c],
-// Q[y] = sum_c V[c] W[y,c]. A row of 2^n entries is handled by
-// tpr = min(256, 2^n) threads; tile t covers rows t * (256 / tpr) onwards.
-// p0 W, p1 U, p2 V, p3 P, p4 Q, u0 n, q0 rows.
-__device__ void body_copy_contract(const Step& st, uint32_t tile, uint32_t ntiles) {
-  __shared__ Fr sp[kBlock], sq[kBlock];
-  const Fr* __restrict__ W = P<const Fr*>(st, 0);
-  const Fr* __restrict__ U = P<const Fr*>(st, 1);
-  const Fr* __restrict__ V = P<const Fr*>(st, 2);
-  const uint32_t n = st.u[0];
-  const uint64_t rows = st.q[0];
-  const uint32_t tpr_log = n < 8 ? n : 8;
-  const uint32_t tpr = 1u << tpr_log;
-  const uint32_t lane = threadIdx.x & (tpr - 1);
-  const uint64_t rows_per_tile = kBlock >> tpr_log;
-  for (uint64_t base = (uint64_t)tile * rows_per_tile; base < rows; base += (uint64_t)ntiles * rows_per_tile) {
-    const uint64_t row = base + (threadIdx.x >> tpr_log);
-    Fr p = fr_zero(), q = fr_zero();
-    if (row < rows) {
-      const uint64_t ncop = 1ull << n;
-      for (uint64_t c = lane; c < ncop; c += tpr) {
-        const Fr w = ldf(W, (row << n) | c);
-        p = fr_add(p, fr_mul(ldf(U, c), w));
-        q = fr_add(q, fr_mul(ldf(V, c), w));
-      }
-    }
-    __syncthreads();
-    sp[threadIdx.x] = p;
-    sq[threadIdx.x] = q;
-    __syncthreads();
-    for (uint32_t s = tpr / 2; s >= 1; s >>= 1) {
-      if (lane < s) {
-        sp[threadIdx.x] = fr_add(sp[threadIdx.x], sp[threadIdx.x + s]);
-        sq[threadIdx.x] = fr_add(sq[threadIdx.x], sq[threadIdx.x + s]);
-      }
-      __syncthreads();
-    }
-    if (lane == 0 && row < rows) {
-      stf(P<Fr*>(st, 3), row, sp[threadIdx.x]);
-      stf(P<Fr*>(st, 4), row, sq[threadIdx.x]);
-    }
-  }
-}
-
-// ST_LOCAL_CONTRACT: column sums over the sub-circuit variables, first stage:
-// part[c * R + k] = sum_{y in chunk k} EqR[y] W[y,c] for R = u1 chunks of rows;
-// one thread per (column, chunk), tile t = column block (t % xb) and chunk (t / xb).
-// p0 W, p1 EqR, p2 part, u0 n, u1 R, q0 rows.
-__device__ void body_local_contract(const Step& st, uint32_t tile, uint32_t ntiles) {
-  const Fr* __restrict__ W = P<const Fr*>(st, 0);
-  const Fr* __restrict__ EqR = P<const Fr*>(st, 1);
-  Fr* __restrict__ part = P<Fr*>(st, 2);
-  const uint32_t n = st.u[0], R = st.u[1];
-  const uint64_t rows = st.q[0], ncop = 1ull << n;
-  const uint64_t xb = (ncop + kBlock - 1) / kBlock;
-  for (uint64_t t = tile; t < xb * R; t += ntiles) {
-    const uint64_t c = (t % xb) * kBlock + threadIdx.x;
-    const uint64_t k = t / xb;
-    if (c >= ncop) continue;
-    const uint64_t per = (rows + R - 1) / R;
-    const uint64_t y0 = k * per, y1 = (y0 + per < rows) ? y0 + per : rows;
-    Fr acc = fr_zero();
-    for (uint64_t y = y0; y < y1; ++y) acc = fr_add(acc, fr_mul(ldf(EqR, y), ldf(W, (y << n) | c)));
-    stf(part, c * R + k, acc);
-  }
-}
-
-// ST_COPY_TABLES: the copy tables of phase 2. A column's R partials are summed
-// by tpc = min(256, R) threads:
-// Wc[c] = sum_k part[c*R + k], Fc[c] = U[c] Fa~ + V[c] Fb~, Kc[c] = U[c] Ka~ + V[c] Kb~.
-// p0 part, p1 U, p2 V, p3 fa_f, p4 fb_f, p5 S, p6 Wc, p7 Fc, p8 Kc, u0 R, q0 ncop.
-__device__ void body_copy_tables(const Step& st, uint32_t tile, uint32_t ntiles) {
-  __shared__ Fr sw[kBlock];
-  const Fr* __restrict__ part = P<const Fr*>(st, 0);
-  const uint32_t R = st.u[0];
-  const uint64_t ncop = st.q[0];
-  const uint32_t tpc_log = 31 - __clz(R < (uint32_t)kBlock ? R : (uint32_t)kBlock);
-  const uint32_t tpc = 1u << tpc_log;
-  const uint32_t lane = threadIdx.x & (tpc - 1);
-  const uint64_t cols_per_tile = kBlock >> tpc_log;
-  const DevState* S = P<const DevState*>(st, 5);
-  for (uint64_t base = (uint64_t)tile * cols_per_tile; base < ncop; base += (uint64_t)ntiles * cols_per_tile) {
-    const uint64_t c = base + (threadIdx.x >> tpc_log);
-    Fr w = fr_zero();
-    if (c < ncop)
-      for (uint32_t k = lane; k < R; k += tpc) w = fr_add(w, ldf(part, c * R + k));
-    __syncthreads();
-    sw[threadIdx.x] = w;
-    __syncthreads();
-    for (uint32_t s = tpc / 2; s >= 1; s >>= 1) {
-      if (lane < s) sw[threadIdx.x] = fr_add(sw[threadIdx.x], sw[threadIdx.x + s]);
-      __syncthreads();
-    }
-    if (lane == 0 && c < ncop) {
-      const Fr u = ldf(P<const Fr*>(st, 1), c), v = ldf(P<const Fr*>(st, 2), c);
-      stf(P<Fr*>(st, 6), c, sw[threadIdx.x]);
-      stf(P<Fr*>(st, 7), c, fr_add(fr_mul(u, *P<const Fr*>(st, 3)), fr_mul(v, *P<const Fr*>(st, 4))));
-      stf(P<Fr*>(st, 8), c, fr_add(fr_mul(u, S->ka_f), fr_mul(v, S->kb_f)));
-    }
-  }
-}
-
-// ST_LOCAL_VALUES: Ka~, Kb~ at the phase-2 sub-circuit point: dot products with
-// EqR (one workgroup). p0 EqR, p1 Ka, p2 Kb, p3 S, q0 rows.
-__device__ void body_local_values(const Step& st, uint32_t, uint32_t) {
-  const Fr* EqR = P<const Fr*>(st, 0);
-  const Fr* Ka = P<const Fr*>(st, 1);
-  const Fr* Kb = P<const Fr*>(st, 2);
-  DevState* S = P<DevState*>(st, 3);
-  Fr acc[2] = {fr_zero(), fr_zero()};
-  for (uint64_t y = threadIdx.x; y < st.q[0]; y += kBlock) {
-    const Fr e = ldf(EqR, y);
-    acc[0] = fr_add(acc[0], fr_mul(e, ldf(Ka, y)));
-    acc[1] = fr_add(acc[1], fr_mul(e, ldf(Kb, y)));
-  }
-  block_reduce<2>(acc);
-  if (threadIdx.x == 0) {
-    S->ka_f = acc[0];
-    S->kb_f = acc[1];
-  }
-}
-
-// ST_STATE_EXPORT / ST_STATE_IMPORT: transcript state bytes <-> device state.
-// p0 S, p1 32-byte buffer.
-__device__ void body_state_export(const Step& st, uint32_t, uint32_t) {
-  const DevState* S = P<const DevState*>(st, 0);
-  uint8_t* out = P<uint8_t*>(st, 1);
-  if (threadIdx.x < 8) {
-    const uint32_t h = S->st[threadIdx.x];
-    out[4 * threadIdx.x + 0] = (uint8_t)(h >> 24);
-    out[4 * threadIdx.x + 1] = (uint8_t)(h >> 16);
-    out[4 * threadIdx.x + 2] = (uint8_t)(h >> 8);
-    out[4 * threadIdx.x + 3] = (uint8_t)h;
-  }
-}
-__device__ void body_state_import(const Step& st, uint32_t, uint32_t) {
-  DevState* S = P<DevState*>(st, 0);
-  const uint8_t* in = P<const uint8_t*>(st, 1);
-  if (threadIdx.x < 8) {
-    const uint8_t* b = in + 4 * threadIdx.x;
-    S->st[threadIdx.x] = ((uint32_t)b[0] << 24) | ((uint32_t)b[1] << 16) | ((uint32_t)b[2] << 8) | b[3];
-  }
-  if (threadIdx.x == 0) S->counter = 0;
-}
-
-#undef GTID
-#undef GSTRIDE
-
-// Runs tile `tile` of a step; for reduction steps the last tile (by the
-// counter in the proof's state) also runs the finisher. Used by the batch kernel.
-__device__ void run_step_tile(const Step& st, uint32_t tile, uint32_t ntiles) {
-  uint32_t* counter = nullptr;
-  switch (st.type) {
-    case ST_WSUM: counter = &P<DevState*>(st, 4)->counter; break;
-    case ST_P1_INIT_ROUND: counter = &P<DevState*>(st, 9)->counter; break;
-    case ST_ROUND_A: counter = &P<DevState*>(st, RoundPtrs<3>::kS)->counter; break;
-    case ST_ROUND_B: counter = &P<DevState*>(st, RoundPtrs<5>::kS)->counter; break;
-    default: break;
-  }
-  switch (st.type) {
-    case ST_TO_MONT: body_to_mont(st, tile, ntiles); break;
-    case ST_FROM_MONT: body_from_mont(st, tile, ntiles); break;
-    case ST_FORWARD: body_forward(st, tile, ntiles); break;
-    case ST_DIGEST: body_digest(st, tile, ntiles); break;
-    case ST_TRANSCRIPT_BEGIN: body_transcript_begin(st, tile, ntiles); break;
-    case ST_SQUEEZE: body_squeeze(st, tile, ntiles); break;
-    case ST_LAYER_BEGIN: body_layer_begin(st, tile, ntiles); break;
-    case ST_EQ: body_eq(st, tile, ntiles); break;
-    case ST_WSUM:
-      body_wsum(st, tile, ntiles);
-      if (last_tile(counter, ntiles)) finish_wsum(st, ntiles);
-      break;
-    case ST_P1_INIT: body_p1_init(st, tile, ntiles); break;
-    case ST_P1_INIT_ROUND:
-      body_p1_init_round(st, tile, ntiles);
-      if (last_tile(counter, ntiles)) finish_p1_init_round(st, ntiles);
-      break;
-    case ST_ROUND_A:
-      body_round<FormA>(st, tile, ntiles);
-      if (last_tile(counter, ntiles)) finish_round_step<FormA>(st, ntiles);
-      break;
-    case ST_ROUND_B:
-      body_round<FormB>(st, tile, ntiles);
-      if (last_tile(counter, ntiles)) finish_round_step<FormB>(st, ntiles);
-      break;
-    case ST_TAIL_A: body_tail<FormA>(st, tile, ntiles); break;
-    case ST_TAIL_B: body_tail<FormB>(st, tile, ntiles); break;
-    case ST_COPY_WEIGHTS: body_copy_weights(st, tile, ntiles); break;
-    case ST_P2_TABLES: body_p2_tables(st, tile, ntiles); break;
-    case ST_COPY_CONTRACT: body_copy_contract(st, tile, ntiles); break;
-    case ST_LOCAL_CONTRACT: body_local_contract(st, tile, ntiles); break;
-    case ST_COPY_TABLES: body_copy_tables(st, tile, ntiles); break;
-    case ST_LOCAL_VALUES: body_local_values(st, tile, ntiles); break;
-    case ST_STATE_EXPORT: body_state_export(st, tile, ntiles); break;
-    case ST_STATE_IMPORT: body_state_import(st, tile, ntiles); break;
-    default: break;
-  }
-}
 
 // ------------------------------------------------------------ plain kernels
 
@@ -821,6 +11,12 @@ __device__ void run_step_tile(const Step& st, uint32_t tile, uint32_t ntiles) {
 // own body needs. The counter of a reduction step lives in the proof's state.
 #define GKR_PLAIN_KERNEL(NAME, TYPE)                                              \
   __global__ void __launch_bounds__(kBlock) NAME(Step st) {                       \
+    run_step_tile_##TYPE(st, blockIdx.x, gridDim.x);                              \
+  }
+// Grid-wide sweeps whose speed depends on latency hiding: at least 3 waves
+// per SIMD (at most 168 VGPRs).
+#define GKR_PLAIN_KERNEL_OCC3(NAME, TYPE)                                         \
+  __global__ void __launch_bounds__(kBlock, 3) NAME(Step st) {                    \
     run_step_tile_##TYPE(st, blockIdx.x, gridDim.x);                              \
   }
 
@@ -874,9 +70,9 @@ GKR_PLAIN_KERNEL(k_layer_begin, layer_begin)
 GKR_PLAIN_KERNEL(k_eq, eq)
 GKR_PLAIN_KERNEL(k_wsum, wsum)
 GKR_PLAIN_KERNEL(k_p1_init, p1_init)
-GKR_PLAIN_KERNEL(k_p1_init_round, p1_init_round)
-GKR_PLAIN_KERNEL(k_round_a, round_a)
-GKR_PLAIN_KERNEL(k_round_b, round_b)
+GKR_PLAIN_KERNEL_OCC3(k_p1_init_round, p1_init_round)
+GKR_PLAIN_KERNEL_OCC3(k_round_a, round_a)
+GKR_PLAIN_KERNEL_OCC3(k_round_b, round_b)
 GKR_PLAIN_KERNEL(k_tail_a, tail_a)
 GKR_PLAIN_KERNEL(k_tail_b, tail_b)
 GKR_PLAIN_KERNEL(k_copy_weights, copy_weights)
@@ -887,123 +83,6 @@ GKR_PLAIN_KERNEL(k_copy_tables, copy_tables)
 GKR_PLAIN_KERNEL(k_local_values, local_values)
 GKR_PLAIN_KERNEL(k_state_export, state_export)
 GKR_PLAIN_KERNEL(k_state_import, state_import)
-
-// ------------------------------------------------------------ batch kernel
-
-// Persistent kernel over up to kMaxBatchJobs step programs. Job j's counters
-// (device memory) are ctr[0] = current step, ctr[1 + s] = tiles of step s
-// claimed, ctr[1 + nsteps + s] = tiles of step s done. A workgroup claims a
-// tile of some job's current step, runs it, and counts it done; the tile that
-// completes a step publishes the next one (release fence, then the store), and
-// the tile that completes a job's last step counts the job finished. Tiles
-// never wait on other tiles, so the kernel always drains: a workgroup leaves
-// when a scan finds no unfinished job, or once ctl[1] (stop) is set - when the
-// step budget is reached or, with stop_on_finish, when any job finishes. A
-// workgroup with no claimable tile while jobs are unfinished sleeps and scans
-// again; the tiles it waits for are running and never wait themselves. A
-// claimed tile is always run to the end, so a later launch continues exactly
-// where this one stopped. ctl[0] = jobs finished in this launch, ctl[2] =
-// steps completed.
-__global__ void __launch_bounds__(kBlock) k_batch(BatchArgs a) {
-  __shared__ uint32_t sh_job, sh_step, sh_tile, sh_state;  // state: 0 work, 1 none, 2 exit
-  __shared__ Step sh_st;
-  uint32_t* ctl = a.ctl;
-  const uint32_t njobs = a.njobs;
-  uint32_t start = (blockIdx.x * 2654435761u) % njobs;
-  for (;;) {
-    if (threadIdx.x == 0) {
-      uint32_t state = 1;
-      if (__hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-        state = 2;
-      } else {
-        bool unfinished = false;
-        for (uint32_t scan = 0; scan < njobs && state == 1; ++scan) {
-          const uint32_t j = (start + scan) % njobs;
-          const BatchJobDev& jb = a.jobs[j];
-          uint32_t* ctr = jb.ctr;
-          const uint32_t s = __hip_atomic_load(&ctr[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-          if (s >= jb.nsteps) continue;
-          unfinished = true;
-          const uint32_t nt = jb.steps[s].ntiles;
-          if (__hip_atomic_load(&ctr[1 + s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= nt) continue;
-          const uint32_t t = atomicAdd(&ctr[1 + s], 1u);
-          if (t < nt) {
-            sh_job = j;
-            sh_step = s;
-            sh_tile = t;
-            state = 0;
-            start = j;  // stay with this job while it has tiles
-          }
-        }
-        if (!unfinished) state = 2;  // every job is finished
-      }
-      sh_state = state;
-    }
-    __syncthreads();
-    const uint32_t state = sh_state;
-    if (state == 2) break;
-    if (state == 1) {
-      if (threadIdx.x == 0) __builtin_amdgcn_s_sleep(8);
-      __syncthreads();
-      continue;
-    }
-    const uint32_t j = sh_job, s = sh_step, tile = sh_tile;
-    const BatchJobDev& jb = a.jobs[j];
-    // copy the step record to LDS (256-byte record, 4-byte words)
-    {
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(&jb.steps[s]);
-      uint32_t* dst = reinterpret_cast<uint32_t*>(&sh_st);
-      for (uint32_t k = threadIdx.x; k < sizeof(Step) / 4; k += kBlock) dst[k] = src[k];
-    }
-    __threadfence();  // acquire: see the writes of the previous steps
-    __syncthreads();
-    run_step_tile(sh_st, tile, sh_st.ntiles);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();  // release this tile's writes
-      uint32_t* ctr = jb.ctr;
-      const uint32_t d = atomicAdd(&ctr[1 + jb.nsteps + s], 1u);
-      if (d == sh_st.ntiles - 1) {
-        __threadfence();
-        const uint32_t done_steps = atomicAdd(&ctl[2], 1u) + 1;
-        __hip_atomic_store(&ctr[0], s + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        if (s + 1 == jb.nsteps) {
-          atomicAdd(&ctl[0], 1u);
-          if (a.stop_on_finish) atomicExch(&ctl[1], 1u);
-        }
-        if (a.step_budget && done_steps >= a.step_budget) atomicExch(&ctl[1], 1u);
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Zero a job's counters (n words) so its program runs from the start.
-__global__ void __launch_bounds__(kBlock) k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
-  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock) p[i] = v;
-}
-
-void launch_batch(const BatchArgs& a, uint32_t workgroups, hipStream_t s) {
-  const int tok = prof_begin(s);
-  k_batch<<<workgroups, kBlock, 0, s>>>(a);
-  if (tok >= 0) prof_end(tok, s, PC_BATCH, 0.0, 0.0);
-}
-
-void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
-  uint64_t g = (n + kBlock - 1) / kBlock;
-  if (g < 1) g = 1;
-  if (g > 4096) g = 4096;
-  k_fill_u32<<<(uint32_t)g, kBlock, 0, s>>>(p, n, v);
-}
-
-uint32_t batch_kernel_max_workgroups_per_cu() {
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch, kBlock, 0) != hipSuccess) {
-    (void)hipGetLastError();
-    return 1;
-  }
-  return nb < 1 ? 1 : (uint32_t)nb;
-}
 
 static const ProfClass kStepClass[ST_COUNT] = {
     PC_CONVERT,        PC_CONVERT, PC_FORWARD, PC_DIGEST,        PC_TRANSCRIPT,    PC_TRANSCRIPT,

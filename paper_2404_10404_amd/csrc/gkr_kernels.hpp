@@ -14,18 +14,12 @@ struct Words8 {
 // Phase 1 and the copy rounds of phase 2: sum_b W[b] G[b] + H[b]; tables (W, G, H).
 struct FormA {
   static constexpr int NT = 3;
-  __device__ static inline void eval(const Fr* x, Fr& acc) {
-    acc = fr_add(acc, fr_add(fr_mul(x[0], x[1]), x[2]));
-  }
 };
 
 // Sub-circuit rounds of phase 2 with the copy factors contracted:
 // sum_b P[b] Fa[b] + Q[b] Fb[b] + Ks[b]; tables (P, Fa, Q, Fb, Ks).
 struct FormB {
   static constexpr int NT = 5;
-  __device__ static inline void eval(const Fr* x, Fr& acc) {
-    acc = fr_add(acc, fr_add(fr_add(fr_mul(x[0], x[1]), fr_mul(x[2], x[3])), x[4]));
-  }
 };
 
 // Pointer slots of round steps over NT tables: src[0..NT), dst[NT..2NT), then

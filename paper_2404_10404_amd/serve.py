@@ -3,13 +3,21 @@
 Requests (a circuit, its inputs, a seed, an arrival time) enter a FIFO queue.
 The server admits the head of the queue when a slot is free and the job's
 device footprint (workspace + proof + inputs + outputs) fits the HBM budget,
-uploads its inputs, records its proof program (a plan) and adds it to the
-running set. The running set is proved by epochs of the persistent batch
-kernel: an epoch ends when any job finishes (or after a step budget), finished
-jobs are retired and their memory returned, newly arrived jobs are admitted,
-and the next epoch continues every unfinished job where it stopped. So
-requests that arrive while others are on the GPU join the running set as
-slots and memory free up, and their work overlaps on the device.
+uploads its inputs and hands it to an executor; running jobs stay resident
+on the device until they finish, then their memory is returned and the next
+requests are admitted. Requests that arrive while others are on the GPU join
+the running set as slots and memory free up, and their work overlaps on the
+device. Two executors:
+
+  StreamExecutor  each admitted proof is enqueued whole (its step launches)
+                  on one of a few HIP streams; jobs on different streams run
+                  concurrently on the hardware queues, so one job's
+                  latency-bound rounds overlap another's bandwidth-bound
+                  sweeps. Completion is seen by polling an event per job.
+  GpuExecutor     the running set is proved by epochs of the persistent
+                  batch kernel; an epoch ends when any job finishes, finished
+                  jobs retire, new ones are admitted, and the next epoch
+                  continues every unfinished job where it stopped.
 
 The plain one-job-at-a-time loop over the same trace is `serve_plain`.
 Latency = completion - arrival; p50/p99 use the nearest-rank definition.
@@ -102,7 +110,9 @@ class Executor:
     def admit(self, r: Request) -> object:
         raise NotImplementedError
 
-    def epoch(self, running: List[object]) -> None:
+    def epoch(self, running: List[object], timeout: Optional[float] = None) -> None:
+        """Advance the running jobs; return once some job has finished or, when
+        `timeout` is given, after about that many seconds (the next arrival)."""
         raise NotImplementedError
 
     def finished(self, slot: object) -> bool:
@@ -136,7 +146,11 @@ def serve(requests: Sequence[Request], executor: Executor, max_slots: int, budge
             if queue:
                 sleep(max(0.0, min(0.05, queue[0].arrival - (clock() - t0))))
             continue
-        executor.epoch([s for _, s in running])
+        # wake up for the next arrival if it could be admitted now
+        timeout = None
+        if queue and len(running) < max_slots and adm.used + queue[0].footprint <= budget_bytes:
+            timeout = max(0.0, queue[0].arrival - (clock() - t0))
+        executor.epoch([s for _, s in running], timeout)
         keep = []
         for r, slot in running:
             if executor.finished(slot):
@@ -179,7 +193,7 @@ class GpuExecutor(Executor):
         plan = gkr.Plan(gkr.make_job(c, d_in, r.seed, out, proof, ws))
         return {"r": r, "plan": plan, "bufs": (d_in, out, proof, ws), "done": False}
 
-    def epoch(self, running):
+    def epoch(self, running, timeout=None):
         live = [s for s in running if not s["done"]]
         for k in range(0, len(live), 64):
             self.gkr.run_batch([s["plan"] for s in live[k:k + 64]], self.ctl, workgroups=self.workgroups,
@@ -199,6 +213,66 @@ class GpuExecutor(Executor):
             result.proof = bytes(proof[: c.proof_bytes].cpu().numpy().tobytes())
             result.outputs = bytes(out.cpu().numpy().tobytes())
         slot["plan"].close()
+        slot["bufs"] = None
+
+
+class StreamExecutor(Executor):
+    """Runs each admitted proof whole on one of `streams` HIP streams."""
+
+    def __init__(self, streams: int = 4, keep_proofs: bool = True, poll_s: float = 1e-4):
+        import torch
+
+        from . import gkr
+        self.gkr = gkr
+        self.torch = torch
+        self.keep = keep_proofs
+        self.poll = poll_s
+        self.streams = [torch.cuda.Stream() for _ in range(max(1, streams))]
+        self.load = [0] * len(self.streams)
+
+    def footprint(self, r: Request) -> int:
+        c = r.circuit
+        return (c.workspace_bytes + c.proof_bytes + 32 * ((1 << c.s(c.depth)) + (1 << c.s(0)))
+                + 64 * 1024)
+
+    def admit(self, r: Request):
+        torch, gkr = self.torch, self.gkr
+        k = min(range(len(self.streams)), key=lambda i: self.load[i])
+        s = self.streams[k]
+        c = r.circuit
+        with torch.cuda.stream(s):
+            d_in = gkr.device_elements(r.inputs)
+            out = torch.empty((1 << c.s(0), 8), dtype=torch.int32, device="cuda")
+            proof = gkr.alloc_bytes(c.proof_bytes)
+            ws = gkr.alloc_bytes(c.workspace_bytes)
+            gkr.prove_circuit(c, d_in, r.seed, out, proof, ws, stream=s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        self.load[k] += 1
+        return {"r": r, "k": k, "ev": ev, "bufs": (d_in, out, proof, ws), "done": False}
+
+    def epoch(self, running, timeout=None):
+        t0 = time.perf_counter()
+        while True:
+            for s in running:
+                if not s["done"] and s["ev"].query():
+                    s["done"] = True
+            if any(s["done"] for s in running):
+                return
+            if timeout is not None and time.perf_counter() - t0 >= timeout:
+                return
+            time.sleep(self.poll)
+
+    def finished(self, slot) -> bool:
+        return slot["done"]
+
+    def retire(self, slot, result: Result):
+        d_in, out, proof, ws = slot["bufs"]
+        c = slot["r"].circuit
+        if self.keep:
+            result.proof = bytes(proof[: c.proof_bytes].cpu().numpy().tobytes())
+            result.outputs = bytes(out.cpu().numpy().tobytes())
+        self.load[slot["k"]] -= 1
         slot["bufs"] = None
 
 

@@ -17,7 +17,8 @@ def _log(msg):
     sys.stdout.flush()
 
 
-def test_results_identical_alone_and_in_the_mix():
+@pytest.mark.parametrize("executor", ["streams", "persistent"])
+def test_results_identical_alone_and_in_the_mix(executor):
     import torch
 
     from paper_2404_10404_amd import gkr, serve
@@ -35,8 +36,9 @@ def test_results_identical_alone_and_in_the_mix():
         reqs.append(serve.Request(rid=k, circuit=c, inputs=inputs, seed=seed, arrival=0.002 * k,
                                   gate_layers=spec.gate_layers))
         refs[k] = op.prove(oc.Circuit.from_synth(spec, wiring), gs.elements_to_ints(inputs), seed).proof_bytes()
-    _log("serving: continuous batching over %d requests" % len(reqs))
-    mixed = serve.serve(reqs, serve.GpuExecutor(), max_slots=4, budget_bytes=1 << 34)
+    _log("serving: continuous batching (%s) over %d requests" % (executor, len(reqs)))
+    ex = serve.StreamExecutor() if executor == "streams" else serve.GpuExecutor()
+    mixed = serve.serve(reqs, ex, max_slots=4, budget_bytes=1 << 34)
     _log("serving: the plain loop")
     alone = serve.serve_plain(reqs)
     for k in range(len(reqs)):

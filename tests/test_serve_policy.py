@@ -35,7 +35,7 @@ class FakeExecutor(serve.Executor):
         self.admit_order.append(r.rid)
         return {"r": r, "left": self.need[r.rid]}
 
-    def epoch(self, running):
+    def epoch(self, running, timeout=None):
         self.epochs += 1
         self.max_running = max(self.max_running, len(running))
         self.max_used = max(self.max_used, sum(self.size[s["r"].rid] for s in running))
