@@ -112,23 +112,36 @@ __device__ void absorb_digest(Sha256State& st, const uint32_t* d) {
 
 __device__ __forceinline__ Fr fr_one_canonical() { return fr_make(1, 0, 0, 0, 0, 0, 0, 0); }
 
+// (1/2) R^2 mod p: the Montgomery product of a Montgomery value x R with it is
+// (x / 2) R^2, the operand that turns a canonical c into the Montgomery form
+// of c x / 2 in one product.
+__device__ __forceinline__ Fr fr_half_r2() {
+  return fr_make(0xcf10b6d4u, 0x2fcd6decu, 0x2e8ae53au, 0x3e19117du, 0xea9e6c71u, 0xa24ce479u, 0x303ff267u,
+                 0x193d8f92u);
+}
+
 // Round message (e0, e1 = claim - e0, e2), run by all 64 lanes of one wave
 // with e0, e2 the same in every lane: write the message to the proof, absorb
 // (e0, e2), take the challenge r, store r and move the claim to
 // g(r) = e0 + r (e1 - e0) + r (r - 1) (e2 - 2 e1 + e0) / 2.
-// Independent products run in different lanes: 4 products on the serial path.
-__device__ __forceinline__ void finish_round_wave(DevState* S, const Fr& e0, const Fr& e2, Fr* r_out,
-                                  uint32_t* msg_out) {
+// Independent products run in different lanes. With c the canonical
+// challenge and mont(x, y) = x y / R: before hashing, lanes form canonical
+// e0, e2, e1 and D1 = d1 R^2, D2 = (d2 / 2) R^2; after it, r = mont(c, R^2),
+// r d1 = mont(c, D1), r d2/2 = mont(c, D2) in parallel, then
+// r (r - 1) d2/2 = mont(r d2/2, r - 1): three products on the serial path.
+__device__ Fr finish_round_wave(DevState* S, const Fr& e0, const Fr& e2, Fr* r_out,
+                                uint32_t* msg_out) {
   const int lane = threadIdx.x & 63;
   const Fr claim = S->claim;
   const Fr e1 = fr_sub(claim, e0);
   const Fr d1 = fr_sub(e1, e0);
   const Fr d2 = fr_add(fr_sub(e2, fr_double(e1)), e0);
-  // lanes 0, 1, 2: canonical e0, canonical e2, d2 / 2
-  Fr a = lane == 0 ? e0 : (lane == 1 ? e2 : d2);
-  Fr b = lane < 2 ? fr_one_canonical() : fr_inv2();
+  // lanes 0..4: canonical e0, e2, e1; D1; D2
+  Fr a = lane == 0 ? e0 : (lane == 1 ? e2 : (lane == 2 ? e1 : (lane == 3 ? d1 : d2)));
+  Fr b = lane < 3 ? fr_one_canonical() : (lane == 3 ? fr_r2() : fr_half_r2());
   Fr prod = fr_mul(a, b);
-  const Fr c0 = shfl_fr(prod, 0), c2 = shfl_fr(prod, 1), d2h = shfl_fr(prod, 2);
+  const Fr c0 = shfl_fr(prod, 0), c2 = shfl_fr(prod, 1), c1 = shfl_fr(prod, 2);
+  const Fr D1 = shfl_fr(prod, 3), D2 = shfl_fr(prod, 4);
   uint32_t w[25];
   Sha256State st = load_state(S);
 #pragma unroll
@@ -140,18 +153,15 @@ __device__ __forceinline__ void finish_round_wave(DevState* S, const Fr& e0, con
     w[17 + k] = bswap32(c2.v[k]);
   }
   st = sha256_fixed<25>(w);
-  const Fr r = fr_mul(accept(st), fr_r2());
+  const Fr c = accept(st);
+  // lanes 0, 1, 2: r, r d1, r d2/2
+  b = lane == 0 ? fr_r2() : (lane == 1 ? D1 : D2);
+  prod = fr_mul(c, b);
+  const Fr r = shfl_fr(prod, 0), rd1 = shfl_fr(prod, 1), rd2h = shfl_fr(prod, 2);
+  const Fr quad = fr_mul(rd2h, fr_sub(r, fr_one()));
   if (lane == 0) {
     stf(r_out, 0, r);
     save_state(S, st);
-  }
-  // lanes 0, 1, 2: r d1, r (r - 1), canonical e1
-  a = lane == 2 ? e1 : r;
-  b = lane == 0 ? d1 : (lane == 1 ? fr_sub(r, fr_one()) : fr_one_canonical());
-  prod = fr_mul(a, b);
-  const Fr rd1 = shfl_fr(prod, 0), rr = shfl_fr(prod, 1), c1 = shfl_fr(prod, 2);
-  const Fr quad = fr_mul(rr, d2h);
-  if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       msg_out[k] = c0.v[k];
@@ -160,6 +170,7 @@ __device__ __forceinline__ void finish_round_wave(DevState* S, const Fr& e0, con
     }
     S->claim = fr_add(fr_add(e0, rd1), quad);
   }
+  return r;
 }
 
 // A phase's final value (one thread): store it, write it to the proof and absorb it.
@@ -427,7 +438,6 @@ __device__ __forceinline__ void finish_reduced_round(const Fr* partials, uint32_
                                      uint32_t* msg) {
   Fr tot[2];
   sum_partials<2>(partials, ntiles, tot);
-  broadcast_from_thread0<2>(tot);
   if (threadIdx.x < 64) finish_round_wave(S, tot[0], tot[1], r_out, msg);
 }
 
@@ -521,11 +531,25 @@ __device__ __forceinline__ void finish_round_step(const Step& st, uint32_t ntile
                        P<uint32_t*>(st, R::kMsg));
 }
 
+// Table k of NT pointers, for a k that varies across lanes (selects, no
+// indexed private array).
+template <int NT, class T>
+__device__ __forceinline__ T pick(T const (&a)[NT], uint32_t k) {
+  T p = a[0];
+#pragma unroll
+  for (int q = 1; q < NT; ++q) p = k == (uint32_t)q ? a[q] : p;
+  return p;
+}
+
 // ST_TAIL_A / ST_TAIL_B: the remaining u0 rounds of a phase in one workgroup,
 // then the final fold. q0 = table size before the pending fold (if any).
 // Pointers: src, dst, rpending, S, r_out, msg, final_out, proof_value. The
 // final value of table 0 is stored in *final_out and, if proof_value is not
 // null, written to the proof and absorbed.
+// Each round runs in two stages over all threads of the workgroup, so that the
+// independent products of a round are spread over every wave: the fold by the
+// pending challenge (one task per table entry, in place after the first
+// round), then the evaluation at t = 0 and t = 2 (one task per pair and t).
 template <class Form>
 __device__ __forceinline__ void body_tail(const Step& st, uint32_t, uint32_t) {
   constexpr int NT = Form::NT;
@@ -542,6 +566,7 @@ __device__ __forceinline__ void body_tail(const Step& st, uint32_t, uint32_t) {
   uint32_t* msg = P<uint32_t*>(st, 2 * NT + 3);
   Fr* final_out = P<Fr*>(st, 2 * NT + 4);
   uint32_t* proof_value = P<uint32_t*>(st, 2 * NT + 5);
+  const uint32_t nthr = blockDim.x;
   uint64_t size = st.q[0];
   const uint32_t rounds = st.u[0];
   __shared__ Fr r_sh;
@@ -549,37 +574,53 @@ __device__ __forceinline__ void body_tail(const Step& st, uint32_t, uint32_t) {
   __syncthreads();
   if (threadIdx.x == 0) r_sh = fold ? ldf(rpending, 0) : fr_zero();
   __syncthreads();
-  for (uint32_t j = 0; j < rounds; ++j) {
-    const uint64_t eval_size = fold ? size / 2 : size;
-    const uint64_t half = eval_size / 2;
-    const Fr r = r_sh;
-    Fr acc[2] = {fr_zero(), fr_zero()};
-    round_range<Form>(src, dst, threadIdx.x, kBlock, half, fold, r, acc[0], acc[1]);
-    block_reduce<2>(acc);
-    broadcast_from_thread0<2>(acc);
-    if (threadIdx.x < 64) {
-      finish_round_wave(S, acc[0], acc[1], r_out + j, msg + 24 * j);
-      if (threadIdx.x == 0) r_sh = ldf(r_out + j, 0);
-    }
-    __syncthreads();
+  for (uint32_t j = 0;; ++j) {
     if (fold) {
+      // fold: entry i of table k becomes src[i] + r (src[i + m] - src[i])
+      const uint64_t m = size / 2;
+      const uint32_t lg = 63 - __clzll(m);
+      const Fr r = r_sh;
+      for (uint64_t t = threadIdx.x; t < NT * m; t += nthr) {
+        const uint32_t k = (uint32_t)(t >> lg);
+        const uint64_t i = t & (m - 1);
+        const Fr* s = pick<NT>(src, k);
+        const Fr a0 = ldf(s, i), a1 = ldf(s, i + m);
+        stf(pick<NT>(dst, k), i, fr_add(a0, fr_mul(r, fr_sub(a1, a0))));
+      }
+      __syncthreads();
 #pragma unroll
       for (int k = 0; k < NT; ++k) src[k] = dst[k];
+      size = m;
     }
-    fold = true;
-    size = eval_size;
-  }
-  if (fold) {  // size is 2 here
-    if (threadIdx.x < NT) {
-      const int k = threadIdx.x;
-      const Fr r = r_sh;
-      const Fr a0 = ldf(src[k], 0), a1 = ldf(src[k], 1);
-      stf(dst[k], 0, fr_add(a0, fr_mul(r, fr_sub(a1, a0))));
+    if (j == rounds) break;
+    // evaluate: task u < size is the pair b = u mod half at t = 0 (u < half) or t = 2
+    const uint64_t half = size / 2;
+    Fr acc[2] = {fr_zero(), fr_zero()};
+    for (uint64_t u = threadIdx.x; u < size; u += nthr) {
+      const bool t2 = u >= half;
+      const uint64_t b = t2 ? u - half : u;
+      Fr x[NT];
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        const Fr lo = ldf(src[k], b), hi = ldf(src[k], b + half);
+        x[k] = t2 ? fr_sub(fr_double(hi), lo) : lo;
+      }
+      Fr v;
+      if constexpr (NT == 3) v = fr_add(fr_mul(x[0], x[1]), x[2]);
+      else v = fr_add(fr_mul_add2(x[0], x[1], x[2], x[3]), x[4]);
+      if (t2) acc[1] = fr_add(acc[1], v);
+      else acc[0] = fr_add(acc[0], v);
+    }
+    block_sum_to_wave0<2>(acc);
+    if (threadIdx.x < 64) {
+      const Fr r = finish_round_wave(S, acc[0], acc[1], r_out + j, msg + 24 * j);
+      if (threadIdx.x == 0) r_sh = r;
     }
     __syncthreads();
+    fold = true;
   }
   if (threadIdx.x == 0) {
-    const Fr v = ldf(fold ? dst[0] : src[0], 0);
+    const Fr v = ldf(src[0], 0);
     if (proof_value) finish_value(S, v, final_out, proof_value);
     else *final_out = v;
   }

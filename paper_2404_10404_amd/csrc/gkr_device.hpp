@@ -89,15 +89,41 @@ __device__ void broadcast_from_thread0(Fr (&v)[NV]) {
 }
 
 // Workgroup sum of NV values, stored as the tile's partials.
+// Sum of NV values over the workgroup (any multiple of 64 threads, at most
+// 1024); the totals are valid in every lane of wave 0.
+template <int NV>
+__device__ __forceinline__ void block_sum_to_wave0(Fr (&v)[NV]) {
+  __shared__ Fr red[NV][16];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = fr_add(v[k], shfl_xor_fr(v[k], off));
+  }
+  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k][wid] = v[k];
+  }
+  __syncthreads();
+  if (wid == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      Fr acc = red[k][0];
+      for (uint32_t w = 1; w < nw; ++w) acc = fr_add(acc, red[k][w]);
+      v[k] = acc;
+    }
+  }
+}
+
+// Per-tile partial sums of a grid-wide reduction (written by thread 0).
 template <int NV>
 __device__ void write_partial(Fr (&v)[NV], Fr* partials, uint32_t tile) {
-  block_reduce<NV>(v);
+  block_sum_to_wave0<NV>(v);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) stf(partials, (uint64_t)tile * NV + k, v[k]);
   }
 }
-
 // Publishes this tile's writes and counts it; true (in every thread) for the
 // last of ntiles tiles, which then sees all tiles' writes. The counter is back
 // at zero afterwards.
@@ -116,16 +142,16 @@ __device__ __forceinline__ bool last_tile(uint32_t* counter, uint32_t ntiles) {
   return last;
 }
 
-// Sum of the partials of ntiles tiles; the totals are valid in thread 0.
+// Sum of the ntiles partials of a grid-wide reduction; valid in every lane of wave 0.
 template <int NV>
 __device__ void sum_partials(const Fr* partials, uint32_t ntiles, Fr (&out)[NV]) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) out[k] = fr_zero();
-  for (uint32_t b = threadIdx.x; b < ntiles; b += kBlock) {
+  for (uint32_t b = threadIdx.x; b < ntiles; b += blockDim.x) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) out[k] = fr_add(out[k], ldf(partials, (uint64_t)b * NV + k));
   }
-  block_reduce<NV>(out);
+  block_sum_to_wave0<NV>(out);
 }
 
 }  // namespace gkr

@@ -14,7 +14,8 @@
 
 namespace gkr {
 
-constexpr int kBlock = 256;             // threads per workgroup for every kernel
+constexpr int kBlock = 256;             // threads per workgroup (grid-wide kernels, batch kernel)
+constexpr int kTailBlock = 512;         // threads of the single-workgroup tail kernels
 constexpr uint32_t kMaxRoundBlocks = 4096;  // cap on workgroups of a reduction launch
 constexpr int kMaxPartialValues = 2;    // reduced values per workgroup
 constexpr uint32_t kChunkWords = 256;   // 1 KiB SHA-256 leaf chunk of a tree digest

@@ -73,8 +73,13 @@ GKR_PLAIN_KERNEL(k_p1_init, p1_init)
 GKR_PLAIN_KERNEL_OCC3(k_p1_init_round, p1_init_round)
 GKR_PLAIN_KERNEL_OCC3(k_round_a, round_a)
 GKR_PLAIN_KERNEL_OCC3(k_round_b, round_b)
-GKR_PLAIN_KERNEL(k_tail_a, tail_a)
-GKR_PLAIN_KERNEL(k_tail_b, tail_b)
+// The single-workgroup tails run with kTailBlock threads (two waves per SIMD).
+#define GKR_TAIL_KERNEL(NAME, TYPE)                                               \
+  __global__ void __launch_bounds__(kTailBlock) NAME(Step st) {                   \
+    run_step_tile_##TYPE(st, blockIdx.x, gridDim.x);                              \
+  }
+GKR_TAIL_KERNEL(k_tail_a, tail_a)
+GKR_TAIL_KERNEL(k_tail_b, tail_b)
 GKR_PLAIN_KERNEL(k_copy_weights, copy_weights)
 GKR_PLAIN_KERNEL(k_p2_tables, p2_tables)
 GKR_PLAIN_KERNEL(k_copy_contract, copy_contract)
@@ -107,8 +112,8 @@ void launch_step(const Step& st, hipStream_t s) {
     case ST_P1_INIT_ROUND: k_p1_init_round<<<grid, block, 0, s>>>(st); break;
     case ST_ROUND_A: k_round_a<<<grid, block, 0, s>>>(st); break;
     case ST_ROUND_B: k_round_b<<<grid, block, 0, s>>>(st); break;
-    case ST_TAIL_A: k_tail_a<<<grid, block, 0, s>>>(st); break;
-    case ST_TAIL_B: k_tail_b<<<grid, block, 0, s>>>(st); break;
+    case ST_TAIL_A: k_tail_a<<<grid, dim3(kTailBlock), 0, s>>>(st); break;
+    case ST_TAIL_B: k_tail_b<<<grid, dim3(kTailBlock), 0, s>>>(st); break;
     case ST_COPY_WEIGHTS: k_copy_weights<<<grid, block, 0, s>>>(st); break;
     case ST_P2_TABLES: k_p2_tables<<<grid, block, 0, s>>>(st); break;
     case ST_COPY_CONTRACT: k_copy_contract<<<grid, block, 0, s>>>(st); break;
