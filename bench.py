@@ -243,7 +243,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serving"])
+    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serving", "copy"])
+    ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--jobs", type=int, default=256)
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--budget-gib", type=float, default=96.0)
@@ -256,6 +257,22 @@ def main():
     import torch
     from paper_2404_10404_amd import gkr
 
+    if args.mode == "copy":
+        # a plain device-to-device copy of known size: the reference for scaling
+        # the HBM traffic counters of the prover's kernels
+        n = args.copy_mib << 20
+        x = torch.empty(n, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"mode": "copy", "bytes_per_copy": n, "copies": args.steps,
+                          "GB_per_s": round(2 * n * args.steps / dt / 1e9, 1)}), flush=True)
+        return
     if args.mode == "serving":
         res = serving_comparison(gkr, args.jobs, args.slots, args.budget_gib)
         cb = res["continuous_batching"]

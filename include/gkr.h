@@ -37,12 +37,16 @@
  *   absorb(t, m)   st = SHA256(st || t || m), t a four-byte tag
  *   accept         v = LE(st) mod 2^254; while v >= p: st = SHA256(st || "GKRC"), recompute v
  *   squeeze        st = SHA256(st || "GKRC"), then accept
- * Statement: absorb("GKRD", circuit digest), absorb("GKRD", tree digest of the
- * inputs), absorb("GKRD", tree digest of the outputs); tree digests hash 1 KiB
- * chunks and then the concatenated chunk digests, recursively. A round absorbs
- * "GKRR" || e0 || e2 and its challenge is `accept` of the new state (e1 is fixed
- * by the running claim, e1 = claim - e0); a phase's final value is absorbed
- * with "GKRV". Challenges alpha, beta and the output point come from squeeze.
+ *   round(e0, e2)  st = C(st, LE(e0) || LE(e2 + 2^254)), then accept
+ * C is the SHA-256 compression function with st as chaining value and one
+ * 64-byte block (bit 254 of the second value, free since values are below p,
+ * marks a round block). Statement: absorb("GKRD", circuit digest),
+ * absorb("GKRD", tree digest of the inputs), absorb("GKRD", tree digest of the
+ * outputs); tree digests hash 1 KiB chunks and then the concatenated chunk
+ * digests, recursively. The round challenge is that of round(e0, e2) (e1 is
+ * fixed by the running claim, e1 = claim - e0); a phase's final value is
+ * absorbed with "GKRV". Challenges alpha, beta and the output point come from
+ * squeeze.
  *
  * Proof layout: for each gate layer i = 0..d-1 with s' = s_{i+1}:
  *   s' phase-1 messages (e0, e1, e2: the round polynomial at t = 0, 1, 2),

@@ -8,14 +8,18 @@ chain so a proof is a deterministic byte string:
   absorb(t, m)   st = SHA256(st || t || m), t a four-byte tag
   accept         v = LE(st) mod 2^254; while v >= p: st = SHA256(st || "GKRC"), v = LE(st) mod 2^254
   squeeze        st = SHA256(st || "GKRC"), then accept
-  round(e0, e2)  absorb("GKRR", e0 || e2), then accept: the round challenge
+  round(e0, e2)  st = C(st, LE(e0) || LE(e2 + 2^254)), then accept: the round challenge
 
-Tags: "GKRD" statement digests, "GKRR" a round message, "GKRV" a layer's
-final value. A round absorbs e0 and e2 only: e1 is fixed by the running claim
-(e1 = claim - e0, which the verifier checks), so the hash still binds the
-whole round polynomial; the proof carries all three values. Tags are four
-bytes so that every absorbed message stays word-aligned for SHA-256. Field
-elements are absorbed as canonical 32-byte little-endian strings.
+C is the SHA-256 compression function (FIPS 180-4, Section 6.2.2) with st as
+the chaining value and one 64-byte block: a round message costs one
+compression. Both values are below p < 2^254, so bit 254 of the second one
+is free; it is set to mark a round block. Tags: "GKRD" statement digests,
+"GKRV" a layer's final value, "GKRC" challenge rehashing. A round absorbs e0
+and e2 only: e1 is fixed by the running claim (e1 = claim - e0, which the
+verifier checks), so the state still binds the whole round polynomial; the
+proof carries all three values. Tags are four bytes so that every absorbed
+message stays word-aligned for SHA-256. Field elements are absorbed as
+canonical 32-byte little-endian strings.
 
 Statement digests (absorbed before any challenge):
   circuit  SHA256(LE32 d || LE32 n || LE32 sigma_0..sigma_d ||
@@ -33,10 +37,61 @@ from .field import P, encode_all, to_bytes
 DOMAIN = b"SISU-GKR-v1"
 CHUNK_BYTES = 1024
 TAG_DIGEST = b"GKRD"
-TAG_ROUND = b"GKRR"
 TAG_VALUE = b"GKRV"
 TAG_CHALLENGE = b"GKRC"
 _MASK254 = (1 << 254) - 1
+_ROUND_MARK = 1 << 254
+_W32 = 0xFFFFFFFF
+
+
+def _primes(count):
+    out, k = [], 2
+    while len(out) < count:
+        if all(k % q for q in out if q * q <= k):
+            out.append(k)
+        k += 1
+    return out
+
+
+def _iroot(n, e):
+    """floor(n^(1/e)) for an integer n >= 0."""
+    lo, hi = 0, 1 << (n.bit_length() // e + 1)
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if mid ** e <= n:
+            lo = mid
+        else:
+            hi = mid - 1
+    return lo
+
+
+# FIPS 180-4 Section 4.2.2 / 5.3.3: the first 32 bits of the fractional parts
+# of the cube roots of the first 64 primes, and of the square roots of the
+# first 8 primes (computed here from that definition).
+SHA256_K = [_iroot(q << 96, 3) & _W32 for q in _primes(64)]
+SHA256_IV = [_iroot(q << 64, 2) & _W32 for q in _primes(8)]
+
+
+def _rotr(x, n):
+    return ((x >> n) | (x << (32 - n))) & _W32
+
+
+def compress(state: bytes, block: bytes) -> bytes:
+    """SHA-256 compression (FIPS 180-4 Section 6.2.2): chaining value `state`
+    (32 bytes, big-endian words) and one 64-byte block."""
+    assert len(state) == 32 and len(block) == 64
+    H = struct.unpack(">8I", state)
+    W = list(struct.unpack(">16I", block))
+    for t in range(16, 64):
+        s0 = _rotr(W[t - 15], 7) ^ _rotr(W[t - 15], 18) ^ (W[t - 15] >> 3)
+        s1 = _rotr(W[t - 2], 17) ^ _rotr(W[t - 2], 19) ^ (W[t - 2] >> 10)
+        W.append((W[t - 16] + s0 + W[t - 7] + s1) & _W32)
+    a, b, c, d, e, f, g, h = H
+    for t in range(64):
+        t1 = (h + (_rotr(e, 6) ^ _rotr(e, 11) ^ _rotr(e, 25)) + ((e & f) ^ (~e & g)) + SHA256_K[t] + W[t]) & _W32
+        t2 = ((_rotr(a, 2) ^ _rotr(a, 13) ^ _rotr(a, 22)) + ((a & b) ^ (a & c) ^ (b & c))) & _W32
+        h, g, f, e, d, c, b, a = g, f, e, (d + t1) & _W32, c, b, a, (t1 + t2) & _W32
+    return struct.pack(">8I", *((x + y) & _W32 for x, y in zip(H, (a, b, c, d, e, f, g, h))))
 
 
 def sha256(data: bytes) -> bytes:
@@ -86,6 +141,7 @@ class Transcript:
         return self.accept()
 
     def round_challenge(self, e0: int, e2: int) -> int:
-        """Absorb a round message (its values at t = 0 and t = 2) and return the challenge."""
-        self.absorb(TAG_ROUND, to_bytes(e0) + to_bytes(e2))
+        """Absorb a round message (its values at t = 0 and t = 2) with one
+        compression and return the challenge."""
+        self.state = compress(self.state, to_bytes(e0) + (e2 | _ROUND_MARK).to_bytes(32, "little"))
         return self.accept()

@@ -122,7 +122,7 @@ __device__ __forceinline__ Fr fr_half_r2() {
 
 // Round message (e0, e1 = claim - e0, e2), run by all 64 lanes of one wave
 // with e0, e2 the same in every lane: write the message to the proof, absorb
-// (e0, e2), take the challenge r, store r and move the claim to
+// (e0, e2) with one SHA-256 compression, take the challenge r, store r and move the claim to
 // g(r) = e0 + r (e1 - e0) + r (r - 1) (e2 - 2 e1 + e0) / 2.
 // Independent products run in different lanes. With c the canonical
 // challenge and mont(x, y) = x y / R: before hashing, lanes form canonical
@@ -142,17 +142,14 @@ __device__ Fr finish_round_wave(DevState* S, const Fr& e0, const Fr& e2, Fr* r_o
   Fr prod = fr_mul(a, b);
   const Fr c0 = shfl_fr(prod, 0), c2 = shfl_fr(prod, 1), c1 = shfl_fr(prod, 2);
   const Fr D1 = shfl_fr(prod, 3), D2 = shfl_fr(prod, 4);
-  uint32_t w[25];
-  Sha256State st = load_state(S);
-#pragma unroll
-  for (int k = 0; k < 8; ++k) w[k] = st.h[k];
-  w[8] = kTagRound;
+  // absorb: one compression of the block LE(e0) || LE(e2 + 2^254)
+  Sha256Block blk;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    w[9 + k] = bswap32(c0.v[k]);
-    w[17 + k] = bswap32(c2.v[k]);
+    blk.w[k] = bswap32(c0.v[k]);
+    blk.w[8 + k] = bswap32(k == 7 ? (c2.v[k] | kRoundMark) : c2.v[k]);
   }
-  st = sha256_fixed<25>(w);
+  Sha256State st = sha256_compress_v(load_state(S), blk);
   const Fr c = accept(st);
   // lanes 0, 1, 2: r, r d1, r d2/2
   b = lane == 0 ? fr_r2() : (lane == 1 ? D1 : D2);

@@ -20,9 +20,11 @@ constexpr uint32_t kMaxRoundBlocks = 4096;  // cap on workgroups of a reduction 
 constexpr int kMaxPartialValues = 2;    // reduced values per workgroup
 constexpr uint32_t kChunkWords = 256;   // 1 KiB SHA-256 leaf chunk of a tree digest
 
-// Transcript tags as big-endian words ("GKRD", "GKRR", "GKRV", "GKRC").
+// Transcript tags as big-endian words ("GKRD", "GKRV", "GKRC").
 constexpr uint32_t kTagDigest = 0x474B5244u;
-constexpr uint32_t kTagRound = 0x474B5252u;
+// A round message is absorbed as one compression block LE(e0) || LE(e2) with
+// bit 254 of e2 (bit 30 of its top limb) set; both values are below p < 2^254.
+constexpr uint32_t kRoundMark = 1u << 30;
 constexpr uint32_t kTagValue = 0x474B5256u;
 constexpr uint32_t kTagChallenge = 0x474B5243u;
 

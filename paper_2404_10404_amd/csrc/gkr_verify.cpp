@@ -140,10 +140,15 @@ struct HostTranscript {
     absorb_words(kTagChallenge, nullptr, 0);
     return accept();
   }
-  // A round absorbs the values at t = 0 and t = 2; e1 is fixed by the claim.
+  // A round absorbs the values at t = 0 and t = 2 (e1 is fixed by the claim)
+  // with one compression of the block LE(e0) || LE(e2 + 2^254).
   Fr round_challenge(const Fr* e) {
-    const Fr m[2] = {e[0], e[2]};
-    absorb_elements(kTagRound, m, 2);
+    Sha256Block blk;
+    for (int k = 0; k < 8; ++k) {
+      blk.w[k] = bswap32(e[0].v[k]);
+      blk.w[8 + k] = bswap32(k == 7 ? (e[2].v[k] | kRoundMark) : e[2].v[k]);
+    }
+    st = sha256_compress_v(st, blk);
     return accept();
   }
 };

@@ -1,5 +1,6 @@
 """Pins of the SHA-256 transcript: FIPS 180-4 vectors, digest structure, determinism."""
 import hashlib
+import random
 import struct
 
 from oracle import field as F
@@ -47,18 +48,42 @@ def test_transcript_chain_by_hand():
     assert v == cand and tr.state == st
 
 
+def _sha256_by_compression(msg: bytes) -> bytes:
+    """SHA-256 through the oracle's compression function: FIPS 180-4 padding
+    (Section 5.1.1) and the initial value, block by block."""
+    pad = msg + b"\x80" + b"\x00" * ((55 - len(msg)) % 64) + (8 * len(msg)).to_bytes(8, "big")
+    st = b"".join(v.to_bytes(4, "big") for v in T.SHA256_IV)
+    for i in range(0, len(pad), 64):
+        st = T.compress(st, pad[i:i + 64])
+    return st
+
+
+def test_compression_function_matches_hashlib():
+    # the first constants as printed in FIPS 180-4
+    assert T.SHA256_K[0] == 0x428A2F98 and T.SHA256_K[63] == 0xC67178F2
+    assert T.SHA256_IV[0] == 0x6A09E667 and T.SHA256_IV[7] == 0x5BE0CD19
+    rng = random.Random(5)
+    for n in (0, 1, 3, 55, 56, 63, 64, 65, 119, 120, 128, 200, 1000):
+        msg = bytes(rng.randrange(256) for _ in range(n))
+        assert _sha256_by_compression(msg) == hashlib.sha256(msg).digest(), n
+
+
 def test_round_challenge_by_hand():
     tr = T.Transcript(8)
     st = tr.state
     e0, e2 = 12345, F.P - 7
     r = tr.round_challenge(e0, e2)
-    st = hashlib.sha256(st + b"GKRR" + e0.to_bytes(32, "little") + e2.to_bytes(32, "little")).digest()
+    # one compression of the block LE(e0) || LE(e2) with bit 254 of e2 set
+    blk = e0.to_bytes(32, "little") + (e2 + (1 << 254)).to_bytes(32, "little")
+    st = T.compress(st, blk)
     while int.from_bytes(st, "little") % (1 << 254) >= F.P:
         st = hashlib.sha256(st + b"GKRC").digest()
     assert r == int.from_bytes(st, "little") % (1 << 254) and tr.state == st
     # the challenge depends on both absorbed values
     t2 = T.Transcript(8)
     assert t2.round_challenge(e0, e2 - 1) != r
+    t3 = T.Transcript(8)
+    assert t3.round_challenge(e0 + 1, e2) != r
 
 
 def test_squeeze_is_uniform_looking_and_in_range():
