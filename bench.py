@@ -65,7 +65,44 @@ def profile_pass(gkr, prover, d_in, seed, steps):
     return out
 
 
-def roofline(prof):
+# Profile class -> kernel, for the traffic records taken with rocprofv3 --pmc.
+CLASS_KERNEL = {"round": "k_round_a", "round_sub": "k_round_b", "tail": "k_tail_a", "tail_sub": "k_tail_b",
+                "phase1_init": "k_p1_init_round", "forward": "k_forward", "copy_contract": "k_copy_contract",
+                "local_contract": "k_local_contract", "digest": "k_digest"}
+KERNEL_SOURCES = ["fr.hpp", "sha256.hpp", "gkr_device.hpp", "gkr_kernels.hpp", "gkr_bodies.hpp", "gkr_kernels.hip"]
+
+
+def kernel_sources_digest():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2404_10404_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_record(kernel, workload):
+    """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE, WRITE_SIZE runs,
+    scaled by a plain copy of known size), from the summaries under profiles/;
+    None when no record exists or the kernel sources changed since."""
+    d = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(d):
+        return None
+    digest = kernel_sources_digest()
+    for name in sorted(os.listdir(d)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(d, name)) as f:
+            for line in f:
+                if line.startswith("traffic-record:"):
+                    rec = json.loads(line[len("traffic-record:"):])
+                    if rec.get("kernel") == kernel and rec.get("workload") == workload:
+                        if rec.get("sources_sha256") != digest:
+                            return None
+                        return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return None
+
+
+def roofline(prof, workload=None):
     name, e = max(prof.items(), key=lambda kv: kv[1]["ms"])
     sec = e["ms"] / 1e3
     gbs = e["bytes"] / sec / 1e9
@@ -80,7 +117,11 @@ def roofline(prof):
              "frac": round(tops / VALU_PEAK_TOPS, 4)}
     r.update({"kernel": name, "launches_per_step": e["launches"],
               "avg_launch_us": round(e["ms"] * 1e3 / max(1, e["launches"]), 2),
-              "hbm_gbs": round(gbs, 1), "alu_tops": round(tops, 3), "traffic": None})
+              "hbm_gbs": round(gbs, 1), "alu_tops": round(tops, 3),
+              "algorithmic_bytes_per_launch": round(e["bytes"] / max(1, e["launches"]))})
+    kern = CLASS_KERNEL.get(name)
+    t = traffic_record(kern, workload) if kern and workload else None
+    r["traffic"] = None if t is None else round(t)
     return r
 
 
@@ -333,7 +374,7 @@ def main():
     }
     if not args.no_profile:
         prof = profile_pass(gkr, prover, d_in, spec.seed, args.profile_steps)
-        line["roofline"] = roofline(prof)
+        line["roofline"] = roofline(prof, args.workload)
         line["kernels"] = {k: {"ms": round(v["ms"], 4), "launches": v["launches"]} for k, v in
                            sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
     if not args.no_cpu_baseline:

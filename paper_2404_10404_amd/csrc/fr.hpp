@@ -73,49 +73,58 @@ GKR_HD Fr fr_inv2() {
                  0x3d9cbfacu, 0x1f37631au);
 }
 
+// 32-bit add and subtract with carry. On the device these are the clang
+// carry-chain builtins, one v_add_co/v_addc (v_sub_co/v_subb) per limb with
+// the carry in VCC; on the host plain C.
+GKR_HD uint32_t adc32(uint32_t a, uint32_t b, uint32_t cin, uint32_t& cout) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_addc(a, b, cin, &cout);
+#else
+  const uint64_t s = (uint64_t)a + b + cin;
+  cout = (uint32_t)(s >> 32);
+  return (uint32_t)s;
+#endif
+}
+GKR_HD uint32_t sbb32(uint32_t a, uint32_t b, uint32_t bin, uint32_t& bout) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_subc(a, b, bin, &bout);
+#else
+  const uint64_t d = (uint64_t)a - b - bin;
+  bout = (uint32_t)(d >> 63);
+  return (uint32_t)d;
+#endif
+}
+
 // a - p if a >= p, else a (a < 2p).
 GKR_HD Fr fr_reduce_once(const Fr& a) {
   Fr t;
-  uint64_t br = 0;
+  uint32_t br = 0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    uint64_t d = (uint64_t)a.v[k] - p_limb(k) - br;
-    t.v[k] = (uint32_t)d;
-    br = d >> 63;
-  }
-  return br ? a : t;
+  for (int k = 0; k < 8; ++k) t.v[k] = sbb32(a.v[k], p_limb(k), br, br);
+  Fr r;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) r.v[k] = br ? a.v[k] : t.v[k];
+  return r;
 }
 
 GKR_HD Fr fr_add(const Fr& a, const Fr& b) {
   Fr s;
-  uint64_t c = 0;
+  uint32_t c = 0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    uint64_t x = (uint64_t)a.v[k] + b.v[k] + c;
-    s.v[k] = (uint32_t)x;
-    c = x >> 32;
-  }
+  for (int k = 0; k < 8; ++k) s.v[k] = adc32(a.v[k], b.v[k], c, c);
   return fr_reduce_once(s);
 }
 
 // a - b; p is added back under a mask (no branch) when the difference borrows.
 GKR_HD Fr fr_sub(const Fr& a, const Fr& b) {
   Fr d;
-  uint64_t br = 0;
+  uint32_t br = 0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    uint64_t x = (uint64_t)a.v[k] - b.v[k] - br;
-    d.v[k] = (uint32_t)x;
-    br = x >> 63;
-  }
-  const uint32_t mask = 0u - (uint32_t)br;
-  uint64_t c = 0;
+  for (int k = 0; k < 8; ++k) d.v[k] = sbb32(a.v[k], b.v[k], br, br);
+  const uint32_t mask = 0u - br;
+  uint32_t c = 0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    uint64_t x = (uint64_t)d.v[k] + (p_limb(k) & mask) + c;
-    d.v[k] = (uint32_t)x;
-    c = x >> 32;
-  }
+  for (int k = 0; k < 8; ++k) d.v[k] = adc32(d.v[k], p_limb(k) & mask, c, c);
   return d;
 }
 
