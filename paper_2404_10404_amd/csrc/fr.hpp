@@ -228,6 +228,49 @@ GKR_HD void frw_mac(FrWide& A, const Fr& a, const Fr& b) {
   A.w[15] += (uint32_t)acc;
 }
 
+// Column accumulator of a sum of products: column k (k < 15) holds
+// sum_{i+j=k} a_i b_j over every product added, as a 64-bit sum with an
+// overflow word. Adding a product costs exactly its 64 multiply-adds (no
+// carry propagation between columns); carries are propagated once, when the
+// accumulator becomes an FrWide. Up to 16 products of reduced values: a
+// column then sums at most 128 terms below 2^64 (below 2^71).
+struct FrCols {
+  uint64_t c[15];
+  uint32_t o[15];
+};
+
+GKR_HD FrCols frc_zero() {
+  FrCols A;
+#pragma unroll
+  for (int k = 0; k < 15; ++k) {
+    A.c[k] = 0;
+    A.o[k] = 0;
+  }
+  return A;
+}
+
+GKR_HD void frc_mac(FrCols& A, const Fr& a, const Fr& b) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) fr_mac_vv(A.c[i + j], A.o[i + j], a.v[i], b.v[j]);
+}
+
+// The 512-bit value of the columns, carries propagated.
+GKR_HD FrWide frc_wide(const FrCols& A) {
+  FrWide W;
+  uint64_t carry = 0;  // below 2^64 + 2^39 after every column: kept as carry + overflow
+#pragma unroll
+  for (int k = 0; k < 15; ++k) {
+    const uint64_t s = carry + A.c[k];
+    const uint32_t top = A.o[k] + (s < carry ? 1u : 0u);
+    W.w[k] = (uint32_t)s;
+    carry = (s >> 32) | ((uint64_t)top << 32);
+  }
+  W.w[15] = (uint32_t)carry;
+  return W;
+}
+
 // Montgomery reduction of an accumulator of at most `Terms` products of
 // reduced values: returns A * R^{-1} mod p, reduced. With p/2^256 < 0.1895,
 // A < Terms * p^2 gives a high half below 0.1895 * Terms * p; subtracting p

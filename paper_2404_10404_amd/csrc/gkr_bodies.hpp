@@ -708,15 +708,15 @@ __device__ __forceinline__ void body_copy_contract(const Step& st, uint32_t tile
       // at most 16 unreduced products per accumulator between reductions
       const uint64_t ncop = 1ull << n;
       for (uint64_t c0 = lane; c0 < ncop; c0 += 16 * (uint64_t)tpr) {
-        FrWide pw = frw_zero(), qw = frw_zero();
+        FrCols pw = frc_zero(), qw = frc_zero();
         const uint64_t c1 = c0 + 16 * (uint64_t)tpr < ncop ? c0 + 16 * (uint64_t)tpr : ncop;
         for (uint64_t c = c0; c < c1; c += tpr) {
           const Fr w = ldf(W, (row << n) | c);
-          frw_mac(pw, ldf(U, c), w);
-          frw_mac(qw, ldf(V, c), w);
+          frc_mac(pw, ldf(U, c), w);
+          frc_mac(qw, ldf(V, c), w);
         }
-        p = fr_add(p, frw_reduce<16>(pw));
-        q = fr_add(q, frw_reduce<16>(qw));
+        p = fr_add(p, frw_reduce<16>(frc_wide(pw)));
+        q = fr_add(q, frw_reduce<16>(frc_wide(qw)));
       }
     }
     __syncthreads();
@@ -757,9 +757,9 @@ __device__ __forceinline__ void body_local_contract(const Step& st, uint32_t til
     Fr acc = fr_zero();
     for (uint64_t ya = y0; ya < y1; ya += 16) {
       const uint64_t yb = ya + 16 < y1 ? ya + 16 : y1;
-      FrWide aw = frw_zero();
-      for (uint64_t y = ya; y < yb; ++y) frw_mac(aw, ldf(EqR, y), ldf(W, (y << n) | c));
-      acc = fr_add(acc, frw_reduce<16>(aw));
+      FrCols aw = frc_zero();
+      for (uint64_t y = ya; y < yb; ++y) frc_mac(aw, ldf(EqR, y), ldf(W, (y << n) | c));
+      acc = fr_add(acc, frw_reduce<16>(frc_wide(aw)));
     }
     stf(part, c * R + k, acc);
   }

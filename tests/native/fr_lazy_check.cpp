@@ -44,14 +44,17 @@ int main() {
   char a[80], b[80];
   while (scanf("%d", &k) == 1) {
     FrWide A = frw_zero();
+    FrCols C = frc_zero();
     Fr first[2][2];
     for (int i = 0; i < k; ++i) {
       if (scanf("%64s %64s", a, b) != 2) return 1;
       Fr x = parse(a), y = parse(b);
       if (i < 2) { first[i][0] = x; first[i][1] = y; }
       frw_mac(A, x, y);
+      frc_mac(C, x, y);
     }
     print(reduce_dyn(A, k));
+    print(reduce_dyn(frc_wide(C), k));
     if (k == 2) print(fr_mul_add2(first[0][0], first[0][1], first[1][0], first[1][1]));
   }
   return 0;

@@ -1,6 +1,7 @@
 """Lazy (unreduced) products of the prover's field code, checked on the host
 against Python integers: sums of up to 16 Montgomery products with a single
-reduction, including the all-(p-1) worst case that bounds the accumulator."""
+reduction (through the carried 512-bit accumulator and through the column
+accumulator), including the all-(p-1) worst case that bounds both."""
 import os
 import random
 import subprocess
@@ -40,7 +41,8 @@ def test_sums_of_products_single_reduction(checker):
     for c in cases:
         want = sum(a * b for a, b in c) * RINV % P
         assert int(out[pos], 16) == want, (len(c), c[:1])
-        pos += 1
+        assert int(out[pos + 1], 16) == want, ("columns", len(c), c[:1])
+        pos += 2
         if len(c) == 2:
             assert int(out[pos], 16) == want
             pos += 1
