@@ -129,10 +129,11 @@ __device__ __forceinline__ Fr fr_half_r2() {
 // e0, e2, e1 and D1 = d1 R^2, D2 = (d2 / 2) R^2; after it, r = mont(c, R^2),
 // r d1 = mont(c, D1), r d2/2 = mont(c, D2) in parallel, then
 // r (r - 1) d2/2 = mont(r d2/2, r - 1): three products on the serial path.
-__device__ Fr finish_round_wave(DevState* S, const Fr& e0, const Fr& e2, Fr* r_out,
-                                uint32_t* msg_out) {
+// The round step on a claim and transcript state held in registers (the
+// same in every lane of the wave): updates both, returns r.
+__device__ __forceinline__ Fr round_step_wave(Fr& claim, Sha256State& state, const Fr& e0, const Fr& e2,
+                                              Fr* r_out, uint32_t* msg_out) {
   const int lane = threadIdx.x & 63;
-  const Fr claim = S->claim;
   const Fr e1 = fr_sub(claim, e0);
   const Fr d1 = fr_sub(e1, e0);
   const Fr d2 = fr_add(fr_sub(e2, fr_double(e1)), e0);
@@ -149,23 +150,35 @@ __device__ Fr finish_round_wave(DevState* S, const Fr& e0, const Fr& e2, Fr* r_o
     blk.w[k] = bswap32(c0.v[k]);
     blk.w[8 + k] = bswap32(k == 7 ? (c2.v[k] | kRoundMark) : c2.v[k]);
   }
-  Sha256State st = sha256_compress_v(load_state(S), blk);
-  const Fr c = accept(st);
+  state = sha256_compress_v(state, blk);
+  const Fr c = accept(state);
   // lanes 0, 1, 2: r, r d1, r d2/2
   b = lane == 0 ? fr_r2() : (lane == 1 ? D1 : D2);
   prod = fr_mul(c, b);
   const Fr r = shfl_fr(prod, 0), rd1 = shfl_fr(prod, 1), rd2h = shfl_fr(prod, 2);
   const Fr quad = fr_mul(rd2h, fr_sub(r, fr_one()));
+  claim = fr_add(fr_add(e0, rd1), quad);
   if (lane == 0) {
     stf(r_out, 0, r);
-    save_state(S, st);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       msg_out[k] = c0.v[k];
       msg_out[8 + k] = c1.v[k];
       msg_out[16 + k] = c2.v[k];
     }
-    S->claim = fr_add(fr_add(e0, rd1), quad);
+  }
+  return r;
+}
+
+// The round step with the claim and state in the proof's device state.
+__device__ Fr finish_round_wave(DevState* S, const Fr& e0, const Fr& e2, Fr* r_out,
+                                uint32_t* msg_out) {
+  Fr claim = S->claim;
+  Sha256State st = load_state(S);
+  const Fr r = round_step_wave(claim, st, e0, e2, r_out, msg_out);
+  if ((threadIdx.x & 63) == 0) {
+    save_state(S, st);
+    S->claim = claim;
   }
   return r;
 }
@@ -568,6 +581,14 @@ __device__ __forceinline__ void body_tail(const Step& st, uint32_t, uint32_t) {
   const uint32_t rounds = st.u[0];
   __shared__ Fr r_sh;
   bool fold = rpending != nullptr;
+  // the running claim and transcript state stay in wave 0's registers for the
+  // whole tail and go back to the device state at its end
+  Fr claim = fr_zero();
+  Sha256State state;
+  if (threadIdx.x < 64) {
+    claim = S->claim;
+    state = load_state(S);
+  }
   __syncthreads();
   if (threadIdx.x == 0) r_sh = fold ? ldf(rpending, 0) : fr_zero();
   __syncthreads();
@@ -608,15 +629,30 @@ __device__ __forceinline__ void body_tail(const Step& st, uint32_t, uint32_t) {
       if (t2) acc[1] = fr_add(acc[1], v);
       else acc[0] = fr_add(acc[0], v);
     }
-    block_sum_to_wave0<2>(acc);
+    if (size <= 64) {
+      // every task is in wave 0: a wave reduction, no workgroup barrier
+      if (threadIdx.x < 64) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+          acc[0] = fr_add(acc[0], shfl_xor_fr(acc[0], off));
+          acc[1] = fr_add(acc[1], shfl_xor_fr(acc[1], off));
+        }
+      }
+    } else {
+      block_sum_to_wave0<2>(acc);
+    }
     if (threadIdx.x < 64) {
-      const Fr r = finish_round_wave(S, acc[0], acc[1], r_out + j, msg + 24 * j);
+      const Fr r = round_step_wave(claim, state, acc[0], acc[1], r_out + j, msg + 24 * j);
       if (threadIdx.x == 0) r_sh = r;
     }
     __syncthreads();
     fold = true;
   }
   if (threadIdx.x == 0) {
+    if (rounds > 0) {
+      save_state(S, state);
+      S->claim = claim;
+    }
     const Fr v = ldf(src[0], 0);
     if (proof_value) finish_value(S, v, final_out, proof_value);
     else *final_out = v;
