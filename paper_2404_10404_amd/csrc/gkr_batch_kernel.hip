@@ -72,12 +72,14 @@ __global__ void __launch_bounds__(kBlock, 3) k_batch(BatchArgs a) {
       uint32_t* dst = reinterpret_cast<uint32_t*>(&sh_st);
       for (uint32_t k = threadIdx.x; k < sizeof(Step) / 4; k += kBlock) dst[k] = src[k];
     }
-    __threadfence();  // acquire: see the writes of the previous steps
+    // acquire (one wave: the L1 and L2 invalidation covers the whole workgroup
+    // after the barrier): see the writes of the previous steps
+    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __syncthreads();
     run_step_tile(sh_st, tile, sh_st.ntiles);
     __syncthreads();
     if (threadIdx.x == 0) {
-      __threadfence();  // release this tile's writes
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // release this tile's writes
       uint32_t* ctr = jb.ctr;
       const uint32_t d = atomicAdd(&ctr[1 + jb.nsteps + s], 1u);
       if (d == sh_st.ntiles - 1) {

@@ -127,18 +127,21 @@ __device__ void write_partial(Fr (&v)[NV], Fr* partials, uint32_t tile) {
 // Publishes this tile's writes and counts it; true (in every thread) for the
 // last of ntiles tiles, which then sees all tiles' writes. The counter is back
 // at zero afterwards.
+// Only the partial sums (written by thread 0) cross tiles here, so thread 0
+// counts the tile with a release read-modify-write (an L2 write-back, no
+// invalidation) and only the last tile pays for an acquire (L2 invalidation
+// on this chip's per-XCD caches).
 __device__ __forceinline__ bool last_tile(uint32_t* counter, uint32_t ntiles) {
   __shared__ int is_last;
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t prev = atomicAdd(counter, 1u);
+    const uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     is_last = (prev == ntiles - 1);
-    if (is_last) atomicExch(counter, 0u);
+    if (is_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   const bool last = is_last;
-  if (last) __threadfence();
+  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return last;
 }
 
