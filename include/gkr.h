@@ -230,10 +230,14 @@ int32_t gkr_verify(const gkr_circuit* circuit, const gkr_fr* inputs, const gkr_f
  * Round-schedule tuning (process-wide; used by the autotuner). Proof bytes
  * never depend on it. tail_log: tables of at most 2^tail_log entries finish
  * their phase in one workgroup (1..20); max_round_blocks: cap on the
- * workgroups of one grid-wide round (1..4096). Errors: GKR_EINVAL.
+ * workgroups of one grid-wide round (1..4096); pairs_per_thread: a grid-wide
+ * round gets ceil(pairs / (256 * pairs_per_thread)) workgroups, capped
+ * (1..1024). Proofs read the tuning when they are queued. Errors: GKR_EINVAL
+ * for a value out of range (nothing is changed). gkr_get_tuning writes the
+ * current values to the non-null pointers.
  */
-int32_t gkr_set_tuning(uint32_t tail_log, uint32_t max_round_blocks);
-int32_t gkr_get_tuning(uint32_t* tail_log, uint32_t* max_round_blocks);
+int32_t gkr_set_tuning(uint32_t tail_log, uint32_t max_round_blocks, uint32_t pairs_per_thread);
+int32_t gkr_get_tuning(uint32_t* tail_log, uint32_t* max_round_blocks, uint32_t* pairs_per_thread);
 
 /*
  * Kernel timing for measurement. While enabled, every launch is bracketed by

@@ -6,15 +6,19 @@ Tunables (none of them changes proof bytes):
                     more in launch and Fiat-Shamir latency than it saves)
   max_round_blocks  cap on the workgroups of a grid-wide round (more tiles:
                     more parallel partial sums for the last tile to add)
+  pairs_per_thread  a grid-wide round gets ceil(pairs / (256 x this)) workgroups
+                    (fewer, longer-lived workgroups for mid-size rounds)
   batch_workgroups  resident workgroups of the persistent batch kernel
 
 The tuner times whole proofs of the given workloads for every setting on a
-grid, keeps the setting with the least total time, and writes the grid and
-the choice to a JSON cache (default: tuning.json next to this file).
+grid, scores a setting by the sum over workloads of its time divided by that
+workload's best time on the grid, keeps the setting with the least score, and
+writes the grid and the choice to a JSON cache (default: tuning.json next to
+this file).
 `load()` applies a cached choice; the binding calls it on first use when the
 cache exists.
 
-    python -m paper_2404_10404_amd.autotune [--workloads c2,c4] [--reps 3]
+    python -m paper_2404_10404_amd.autotune [--workloads c2,c3,c4] [--reps 3]
 """
 from __future__ import annotations
 
@@ -37,7 +41,7 @@ def load(path: str = CACHE) -> dict | None:
     from . import gkr
     best = rec.get("best", {})
     if "tail_log" in best and "max_round_blocks" in best:
-        gkr.set_tuning(int(best["tail_log"]), int(best["max_round_blocks"]))
+        gkr.set_tuning(int(best["tail_log"]), int(best["max_round_blocks"]), int(best.get("pairs_per_thread", 1)))
     return rec
 
 
@@ -60,7 +64,7 @@ def _time(fn, reps):
     return (time.perf_counter() - t0) / reps
 
 
-def tune(workloads=("c2",), tail_logs=(6, 7, 8, 9, 10, 11, 12), blocks=(512, 1024, 2048, 4096),
+def tune(workloads=("c2",), tail_logs=(8, 9, 10, 11), blocks=(512, 1024, 2048, 4096), ppts=(1, 2, 4),
          reps=3, path: str = CACHE) -> dict:
     import torch
 
@@ -71,16 +75,20 @@ def tune(workloads=("c2",), tail_logs=(6, 7, 8, 9, 10, 11, 12), blocks=(512, 102
     grid = []
     for tl in tail_logs:
         for mb in blocks:
-            gkr.set_tuning(tl, mb)
-            times = {w: _time(fn, reps) for w, fn in fns.items()}
-            grid.append({"tail_log": tl, "max_round_blocks": mb, "seconds": times,
-                         "total": sum(times.values())})
-            print("tail_log %2d  max_round_blocks %4d  %s" % (tl, mb, {k: round(v * 1e3, 3) for k, v in times.items()}),
-                  flush=True)
-    best = min(grid, key=lambda g: g["total"])
+            for ppt in ppts:
+                gkr.set_tuning(tl, mb, ppt)
+                times = {w: _time(fn, reps) for w, fn in fns.items()}
+                grid.append({"tail_log": tl, "max_round_blocks": mb, "pairs_per_thread": ppt, "seconds": times})
+                print("tail_log %2d  max_round_blocks %4d  pairs_per_thread %d  %s"
+                      % (tl, mb, ppt, {k: round(v * 1e3, 3) for k, v in times.items()}), flush=True)
+    best_t = {w: min(g["seconds"][w] for g in grid) for w in fns}
+    for g in grid:
+        g["score"] = sum(g["seconds"][w] / best_t[w] for w in fns)
+    best = min(grid, key=lambda g: g["score"])
     rec = {"device": torch.cuda.get_device_name(0), "workloads": list(fns), "reps": reps, "grid": grid,
-           "best": {"tail_log": best["tail_log"], "max_round_blocks": best["max_round_blocks"]}}
-    gkr.set_tuning(best["tail_log"], best["max_round_blocks"])
+           "best": {"tail_log": best["tail_log"], "max_round_blocks": best["max_round_blocks"],
+                    "pairs_per_thread": best["pairs_per_thread"]}}
+    gkr.set_tuning(best["tail_log"], best["max_round_blocks"], best["pairs_per_thread"])
     if "c4" in workloads:
         rec["batch"] = tune_batch(gkr, reps)
         rec["best"]["batch_workgroups"] = rec["batch"]["best"]
@@ -106,7 +114,7 @@ def tune_batch(gkr, reps) -> dict:
     ctl = torch.zeros(4, dtype=torch.int32, device="cuda")
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     res = {}
-    for wg in (cus // 2, cus, 2 * cus, 4 * cus):
+    for wg in (cus // 4, cus // 2, (3 * cus) // 4, cus, (3 * cus) // 2, 2 * cus):
         def run():
             for p in plans:
                 p.reset()
@@ -119,7 +127,7 @@ def tune_batch(gkr, reps) -> dict:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workloads", default="c2,c4")
+    ap.add_argument("--workloads", default="c2,c3,c4")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=CACHE)
     a = ap.parse_args()

@@ -303,7 +303,8 @@ template <int NT>
 void Program::round(const Fr* const* src, Fr* const* dst, uint64_t half, const Fr* rprev, DevState* S,
                     Fr* partials, Fr* r_out, uint32_t* msg, const Tuning& tun) {
   using R = RoundPtrs<NT>;
-  Step st = mk(NT == 3 ? ST_ROUND_A : ST_ROUND_B, tiles_for(half, tun.max_round_blocks));
+  Step st = mk(NT == 3 ? ST_ROUND_A : ST_ROUND_B,
+               tiles_for((half + tun.pairs_per_thread - 1) / tun.pairs_per_thread, tun.max_round_blocks));
   for (int k = 0; k < NT; ++k) {
     st.p[k] = src[k];
     st.p[NT + k] = dst[k];

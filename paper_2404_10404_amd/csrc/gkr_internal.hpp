@@ -94,8 +94,9 @@ struct Step {
 
 // Tunables of the round schedule (autotuned; see gkr_tuning.*).
 struct Tuning {
-  uint32_t tail_log;        // single-workgroup tail once a table has <= 2^tail_log entries
-  uint32_t max_round_blocks;
+  uint32_t tail_log;          // single-workgroup tail once a table has <= 2^tail_log entries
+  uint32_t max_round_blocks;  // cap on the workgroups of a grid-wide round
+  uint32_t pairs_per_thread;  // a grid-wide round gives each thread at least this many pairs
 };
 
 // Device buffers of one proof, carved out of the caller's workspace.

@@ -102,7 +102,8 @@ def _apply_tuning_cache(L):
     with open(TUNING_CACHE) as f:
         best = json.load(f).get("best", {})
     if "tail_log" in best and "max_round_blocks" in best:
-        _check_with(L, L.gkr_set_tuning(int(best["tail_log"]), int(best["max_round_blocks"])))
+        _check_with(L, L.gkr_set_tuning(int(best["tail_log"]), int(best["max_round_blocks"]),
+                                        int(best.get("pairs_per_thread", 1))))
     _tuned.update(best)
 
 
@@ -293,9 +294,9 @@ def _batch_lib():
         L.gkr_plan_progress.restype = _i32
         L.gkr_prove_batch.argtypes = [ctypes.POINTER(Job), _u32, _vp]
         L.gkr_prove_batch.restype = _i32
-        L.gkr_set_tuning.argtypes = [_u32, _u32]
+        L.gkr_set_tuning.argtypes = [_u32, _u32, _u32]
         L.gkr_set_tuning.restype = _i32
-        L.gkr_get_tuning.argtypes = [ctypes.POINTER(_u32), ctypes.POINTER(_u32)]
+        L.gkr_get_tuning.argtypes = [ctypes.POINTER(_u32), ctypes.POINTER(_u32), ctypes.POINTER(_u32)]
         L.gkr_get_tuning.restype = _i32
         L._batch_ready = True
     return L
@@ -354,11 +355,11 @@ def prove_batch(jobs: Sequence[Job], stream=None):
     _check(_batch_lib().gkr_prove_batch(arr, len(jobs), _stream(stream)))
 
 
-def set_tuning(tail_log: int, max_round_blocks: int):
-    _check(_batch_lib().gkr_set_tuning(tail_log, max_round_blocks))
+def set_tuning(tail_log: int, max_round_blocks: int, pairs_per_thread: int = 1):
+    _check(_batch_lib().gkr_set_tuning(tail_log, max_round_blocks, pairs_per_thread))
 
 
-def get_tuning() -> Tuple[int, int]:
-    a, b = _u32(0), _u32(0)
-    _check(_batch_lib().gkr_get_tuning(ctypes.byref(a), ctypes.byref(b)))
-    return a.value, b.value
+def get_tuning() -> Tuple[int, int, int]:
+    a, b, c = _u32(0), _u32(0), _u32(0)
+    _check(_batch_lib().gkr_get_tuning(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value

@@ -104,3 +104,17 @@ def test_circuit_validation():
     assert e.value.code == gkr.GKR_EUNSUPPORTED
     with pytest.raises(gkr.GkrError):
         gkr.Circuit(0, 0, [2], [])
+
+
+def test_tuning_round_trip_and_ranges():
+    from paper_2404_10404_amd import gkr
+    old = gkr.get_tuning()
+    try:
+        gkr.set_tuning(9, 512, 2)
+        assert gkr.get_tuning() == (9, 512, 2)
+        for bad in [(0, 512, 1), (21, 512, 1), (9, 0, 1), (9, 4097, 1), (9, 512, 0), (9, 512, 1025)]:
+            with pytest.raises(RuntimeError):
+                gkr.set_tuning(*bad)
+            assert gkr.get_tuning() == (9, 512, 2)  # a rejected setting changes nothing
+    finally:
+        gkr.set_tuning(*old)
