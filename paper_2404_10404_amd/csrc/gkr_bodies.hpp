@@ -844,10 +844,17 @@ __device__ __forceinline__ void body_local_values(const Step& st, uint32_t, uint
   const Fr* Kb = P<const Fr*>(st, 2);
   DevState* S = P<DevState*>(st, 3);
   Fr acc[2] = {fr_zero(), fr_zero()};
-  for (uint64_t y = threadIdx.x; y < st.q[0]; y += kBlock) {
-    const Fr e = ldf(EqR, y);
-    acc[0] = fr_add(acc[0], fr_mul(e, ldf(Ka, y)));
-    acc[1] = fr_add(acc[1], fr_mul(e, ldf(Kb, y)));
+  // lazy sums: at most 16 unreduced products per column accumulator
+  for (uint64_t y0 = threadIdx.x; y0 < st.q[0]; y0 += 16 * kBlock) {
+    FrCols a = frc_zero(), b = frc_zero();
+    const uint64_t y1 = y0 + 16 * kBlock < st.q[0] ? y0 + 16 * kBlock : st.q[0];
+    for (uint64_t y = y0; y < y1; y += kBlock) {
+      const Fr e = ldf(EqR, y);
+      frc_mac(a, e, ldf(Ka, y));
+      frc_mac(b, e, ldf(Kb, y));
+    }
+    acc[0] = fr_add(acc[0], frw_reduce<16>(frc_wide(a)));
+    acc[1] = fr_add(acc[1], frw_reduce<16>(frc_wide(b)));
   }
   block_reduce<2>(acc);
   if (threadIdx.x == 0) {

@@ -13,6 +13,14 @@
 namespace gkr {
 
 GKR_HD uint32_t rotr32(uint32_t x, int n) { return (x >> n) | (x << (32 - n)); }
+// a ^ b ^ c: one three-input bit operation on gfx950 (truth table 0x96).
+GKR_HD uint32_t xor3_32(uint32_t a, uint32_t b, uint32_t c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+  return a ^ b ^ c;
+#endif
+}
 GKR_HD uint32_t bswap32(uint32_t x) {
   return (x >> 24) | ((x >> 8) & 0xff00u) | ((x << 8) & 0xff0000u) | (x << 24);
 }
@@ -51,7 +59,17 @@ GKR_HD Sha256State sha256_iv() {
 // One compression of a 16-word (big-endian) block into the chaining value.
 // The 64 rounds run as four passes of 16 unrolled rounds over a rolling
 // 16-word schedule, so each inlined copy stays small.
+// On the device the working variables are pinned to vector registers: with
+// wave-uniform inputs the compiler would otherwise split the rounds between
+// the scalar unit and the vector unit (rotations), paying a register
+// transfer per rotation.
 GKR_HD Sha256State sha256_compress_v(Sha256State st, Sha256Block blk) {
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+  for (int k = 0; k < 8; ++k) asm volatile("" : "+v"(st.h[k]));
+#pragma unroll
+  for (int k = 0; k < 16; ++k) asm volatile("" : "+v"(blk.w[k]));
+#endif
   uint32_t a = st.h[0], b = st.h[1], c = st.h[2], d = st.h[3];
   uint32_t e = st.h[4], f = st.h[5], g = st.h[6], h = st.h[7];
   for (int j = 0; j < 64; j += 16) {
@@ -60,15 +78,15 @@ GKR_HD Sha256State sha256_compress_v(Sha256State st, Sha256Block blk) {
       uint32_t wi = blk.w[i];
       if (j > 0) {
         const uint32_t w15 = blk.w[(i + 1) & 15], w2 = blk.w[(i + 14) & 15];
-        const uint32_t s0 = rotr32(w15, 7) ^ rotr32(w15, 18) ^ (w15 >> 3);
-        const uint32_t s1 = rotr32(w2, 17) ^ rotr32(w2, 19) ^ (w2 >> 10);
+        const uint32_t s0 = xor3_32(rotr32(w15, 7), rotr32(w15, 18), w15 >> 3);
+        const uint32_t s1 = xor3_32(rotr32(w2, 17), rotr32(w2, 19), w2 >> 10);
         wi = blk.w[i] + s0 + blk.w[(i + 9) & 15] + s1;
         blk.w[i] = wi;
       }
-      const uint32_t S1 = rotr32(e, 6) ^ rotr32(e, 11) ^ rotr32(e, 25);
+      const uint32_t S1 = xor3_32(rotr32(e, 6), rotr32(e, 11), rotr32(e, 25));
       const uint32_t ch = (e & f) ^ (~e & g);
       const uint32_t t1 = h + S1 + ch + kSha256K[j + i] + wi;
-      const uint32_t S0 = rotr32(a, 2) ^ rotr32(a, 13) ^ rotr32(a, 22);
+      const uint32_t S0 = xor3_32(rotr32(a, 2), rotr32(a, 13), rotr32(a, 22));
       const uint32_t maj = (a & b) ^ (a & c) ^ (b & c);
       const uint32_t t2 = S0 + maj;
       h = g; g = f; f = e; e = d + t1;

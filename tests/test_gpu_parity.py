@@ -86,6 +86,30 @@ def test_prove_circuit_bit_exact(gkr, shape):
     assert pr.proof_bytes() == proof
 
 
+@pytest.mark.parametrize("shape", [(2, 4, (8, 9, 8), 11, (1, 2)), (2, 0, (12, 11, 12), 12, (1, 2)),
+                                   (2, 9, (4, 3, 4), 16, (1, 2))], ids=["grid", "subcircuit", "copies"])
+def test_tuning_never_changes_proof_bytes(gkr, shape):
+    """Every schedule (tails from 2 to 2^16 entries, one to 4096 round
+    workgroups, several pairs per thread) gives the oracle's bytes."""
+    import torch
+    depth, n, sig, seed, mu = shape
+    spec = gs.CircuitSpec(depth=depth, log_copies=n, log_sub_width=sig, mu=mu, seed=seed)
+    wiring, inputs, ocirc, layers, pt = _oracle_case(spec)
+    c = gkr.Circuit.from_synth(spec, wiring)
+    pr = gkr.Prover(c)
+    d_in = gkr.device_elements(inputs)
+    old = gkr.get_tuning()
+    try:
+        for tun in [(1, 1, 1), (1, 4096, 1), (4, 7, 3), (6, 512, 1), (9, 64, 2), (12, 512, 1), (16, 4096, 5)]:
+            _log("tuning %s on %s" % (tun, shape))
+            gkr.set_tuning(*tun)
+            pr.prove(d_in, seed)
+            torch.cuda.synchronize()
+            assert pr.proof_bytes() == pt.proof_bytes(), tun
+    finally:
+        gkr.set_tuning(*old)
+
+
 def test_layer_entry_points_compose_and_resume(gkr):
     """transcript_init + output_claim + prove_layer (each layer resumed from the
     oracle's transcript state) give the oracle's bytes layer by layer."""
