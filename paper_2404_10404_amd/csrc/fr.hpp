@@ -311,11 +311,45 @@ GKR_HD Fr frw_reduce(const FrWide& A) {
 }
 
 // a*b + c*d with one reduction.
+// Product scanning of both products and the Montgomery reduction in one
+// pass (the FIPS schedule with two product terms per column): a*b + c*d <
+// 2p^2 < pR, so the result is below 2p before the final subtraction; a
+// column sums at most 24 terms below 2^64, well inside the 96-bit
+// accumulator.
 GKR_HD Fr fr_mul_add2(const Fr& a, const Fr& b, const Fr& c, const Fr& d) {
-  FrWide A = frw_zero();
-  frw_mac(A, a, b);
-  frw_mac(A, c, d);
-  return frw_reduce<2>(A);
+  uint32_t m[8];
+  Fr r;
+  uint64_t acc = 0;
+  uint32_t ov = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+#pragma unroll
+    for (int j = 0; j < k; ++j) {
+      fr_mac_vv(acc, ov, a.v[j], b.v[k - j]);
+      fr_mac_vv(acc, ov, c.v[j], d.v[k - j]);
+      fr_mac_vs(acc, ov, m[j], p_limb(k - j));
+    }
+    fr_mac_vv(acc, ov, a.v[k], b.v[0]);
+    fr_mac_vv(acc, ov, c.v[k], d.v[0]);
+    m[k] = (uint32_t)acc * GKR_NINV;
+    fr_mac_vs(acc, ov, m[k], GKR_P0);
+    acc = (acc >> 32) | ((uint64_t)ov << 32);
+    ov = 0;
+  }
+#pragma unroll
+  for (int k = 8; k < 15; ++k) {
+#pragma unroll
+    for (int j = k - 7; j < 8; ++j) {
+      fr_mac_vv(acc, ov, a.v[j], b.v[k - j]);
+      fr_mac_vv(acc, ov, c.v[j], d.v[k - j]);
+      fr_mac_vs(acc, ov, m[j], p_limb(k - j));
+    }
+    r.v[k - 8] = (uint32_t)acc;
+    acc = (acc >> 32) | ((uint64_t)ov << 32);
+    ov = 0;
+  }
+  r.v[7] = (uint32_t)acc;
+  return fr_reduce_once(r);
 }
 
 // Montgomery product a*b*R^{-1} mod p. Host: coarsely integrated operand

@@ -170,6 +170,8 @@ Workspace bind_workspace(const gkr_circuit& c, void* base) {
 constexpr uint32_t kSweepTiles = 65535u * 8;  // grid-stride cap of plain sweeps
 constexpr double kE = 32.0;                   // bytes per field element
 
+constexpr uint32_t kInitRoundBlocks = 2048;  // workgroups of the fused table build + first round
+
 static uint32_t tiles_for(uint64_t n, uint32_t cap) {
   uint64_t g = (n + kBlock - 1) / kBlock;
   if (g < 1) g = 1;
@@ -283,7 +285,9 @@ void Program::p1_init_round(const Fr* W, Fr* G, Fr* H, const LayerWiring& lw, co
                             const Fr* bV, const Fr* Cu, const Fr* Cv, uint32_t n, uint64_t half,
                             uint64_t gates, DevState* S, Fr* partials, Fr* r_out, uint32_t* msg,
                             const Tuning& tun) {
-  Step st = mk(ST_P1_INIT_ROUND, tiles_for(half, tun.max_round_blocks));
+  // at least four pairs per thread, up to kInitRoundBlocks workgroups (full
+  // occupancy on the big tables whatever the round cap)
+  Step st = mk(ST_P1_INIT_ROUND, tiles_for((half + 3) / 4, kInitRoundBlocks));
   p1_common(st, W, G, H, lw, aU, bV, Cu, Cv, n);
   st.q[0] = half;
   st.p[9] = S; st.p[10] = partials; st.p[11] = r_out; st.p[12] = msg;

@@ -490,14 +490,26 @@ __device__ __forceinline__ void round_pair(const Fr* const* src, Fr* const* dst,
     acc0 = fr_add(acc0, lo);
     acc2 = fr_add(acc2, fr_sub(fr_double(hi), lo));
   }
-#pragma unroll
-  for (int k = 0; k + 1 < NT; k += 2) {
+  if constexpr (NT == 3) {
     __builtin_amdgcn_sched_barrier(0);
     Fr xl, xh, yl, yh;
-    pair_entries<Fold>(src[k], dst[k], b, half, r, xl, xh);
-    pair_entries<Fold>(src[k + 1], dst[k + 1], b, half, r, yl, yh);
+    pair_entries<Fold>(src[0], dst[0], b, half, r, xl, xh);
+    pair_entries<Fold>(src[1], dst[1], b, half, r, yl, yh);
     acc0 = fr_add(acc0, fr_mul(xl, yl));
     acc2 = fr_add(acc2, fr_mul(fr_sub(fr_double(xh), xl), fr_sub(fr_double(yh), yl)));
+  } else {
+    // both product pairs of a FormB pair at once: one reduction per point
+    __builtin_amdgcn_sched_barrier(0);
+    Fr pl, ph, fl, fh;
+    pair_entries<Fold>(src[0], dst[0], b, half, r, pl, ph);
+    pair_entries<Fold>(src[1], dst[1], b, half, r, fl, fh);
+    __builtin_amdgcn_sched_barrier(0);
+    Fr ql, qh, gl, gh;
+    pair_entries<Fold>(src[2], dst[2], b, half, r, ql, qh);
+    pair_entries<Fold>(src[3], dst[3], b, half, r, gl, gh);
+    acc0 = fr_add(acc0, fr_mul_add2(pl, fl, ql, gl));
+    acc2 = fr_add(acc2, fr_mul_add2(fr_sub(fr_double(ph), pl), fr_sub(fr_double(fh), fl),
+                                    fr_sub(fr_double(qh), ql), fr_sub(fr_double(gh), gl)));
   }
   __builtin_amdgcn_sched_barrier(0);
 }
