@@ -35,9 +35,10 @@
  * Fiat-Shamir transcript (non-interactive form of the verifier's challenges):
  *   init           st = SHA256("SISU-GKR-v1" || LE64(seed))
  *   absorb(t, m)   st = SHA256(st || t || m), t a four-byte tag
- *   accept         v = LE(st) mod 2^254; while v >= p: st = SHA256(st || "GKRC"), recompute v
+ *   accept         v = LE(st) mod 2^254; while v >= p: st = SHA256(st || "GKRC"), recompute v;
+ *                  the challenge is v * 2^-256 mod p
  *   squeeze        st = SHA256(st || "GKRC"), then accept
- *   round(e0, e2)  st = C(st, LE(e0) || LE(e2 + 2^254)), then accept
+ *   round(e0, e2)  st = C(st, LE(e0 * 2^256 mod p) || LE((e2 * 2^256 mod p) + 2^254)), then accept
  * C is the SHA-256 compression function with st as chaining value and one
  * 64-byte block (bit 254 of the second value, free since values are below p,
  * marks a round block). Statement: absorb("GKRD", circuit digest),

@@ -6,14 +6,19 @@ chain so a proof is a deterministic byte string:
 
   init           st = SHA256("SISU-GKR-v1" || LE64(seed))
   absorb(t, m)   st = SHA256(st || t || m), t a four-byte tag
-  accept         v = LE(st) mod 2^254; while v >= p: st = SHA256(st || "GKRC"), v = LE(st) mod 2^254
+  accept         v = LE(st) mod 2^254; while v >= p: st = SHA256(st || "GKRC"), v = LE(st) mod 2^254;
+                 the challenge is v * 2^-256 mod p
   squeeze        st = SHA256(st || "GKRC"), then accept
-  round(e0, e2)  st = C(st, LE(e0) || LE(e2 + 2^254)), then accept: the round challenge
+  round(e0, e2)  st = C(st, LE(e0 * 2^256 mod p) || LE((e2 * 2^256 mod p) + 2^254)), then accept
 
 C is the SHA-256 compression function (FIPS 180-4, Section 6.2.2) with st as
 the chaining value and one 64-byte block: a round message costs one
-compression. Both values are below p < 2^254, so bit 254 of the second one
-is free; it is set to mark a round block. Tags: "GKRD" statement digests,
+compression. The challenge v * 2^-256 mod p is uniform on [0, p) like v (a
+fixed bijection), and a round hashes e * 2^256 mod p (also a bijection of e);
+both are the Montgomery representations (R = 2^256) a prover computing in
+Montgomery form holds, so it hashes and takes challenges without
+conversions. Both hashed values are below p < 2^254, so bit 254 of the
+second one is free; it is set to mark a round block. Tags: "GKRD" statement digests,
 "GKRV" a layer's final value, "GKRC" challenge rehashing. A round absorbs e0
 and e2 only: e1 is fixed by the running claim (e1 = claim - e0, which the
 verifier checks), so the state still binds the whole round polynomial; the
@@ -41,6 +46,8 @@ TAG_VALUE = b"GKRV"
 TAG_CHALLENGE = b"GKRC"
 _MASK254 = (1 << 254) - 1
 _ROUND_MARK = 1 << 254
+_R = (1 << 256) % P
+_RINV = pow(1 << 256, -1, P)
 _W32 = 0xFFFFFFFF
 
 
@@ -129,12 +136,13 @@ class Transcript:
         self.absorb(tag, b"".join(to_bytes(v) for v in values))
 
     def accept(self) -> int:
-        """The current state as a challenge, rehashed with "GKRC" until below p."""
+        """The current state as a challenge: rehash with "GKRC" until the
+        254-bit value v is below p; the challenge is v * 2^-256 mod p."""
         v = int.from_bytes(self.state, "little") & _MASK254
         while v >= P:
             self.state = sha256(self.state + TAG_CHALLENGE)
             v = int.from_bytes(self.state, "little") & _MASK254
-        return v
+        return v * _RINV % P
 
     def squeeze(self) -> int:
         self.state = sha256(self.state + TAG_CHALLENGE)
@@ -143,5 +151,6 @@ class Transcript:
     def round_challenge(self, e0: int, e2: int) -> int:
         """Absorb a round message (its values at t = 0 and t = 2) with one
         compression and return the challenge."""
-        self.state = compress(self.state, to_bytes(e0) + (e2 | _ROUND_MARK).to_bytes(32, "little"))
+        blk = to_bytes(e0 * _R % P) + ((e2 * _R % P) | _ROUND_MARK).to_bytes(32, "little")
+        self.state = compress(self.state, blk)
         return self.accept()

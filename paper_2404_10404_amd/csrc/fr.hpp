@@ -128,6 +128,21 @@ GKR_HD Fr fr_sub(const Fr& a, const Fr& b) {
   return d;
 }
 
+// a / 2 (of a reduced value): a >> 1 when a is even, (a + p) >> 1 when odd
+// (a + p < 2^255). Halving a Montgomery form halves the value it represents.
+GKR_HD Fr fr_half(const Fr& a) {
+  const uint32_t mask = 0u - (a.v[0] & 1u);
+  Fr t;
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) t.v[k] = adc32(a.v[k], p_limb(k) & mask, c, c);
+  Fr r;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) r.v[k] = (t.v[k] >> 1) | (t.v[k + 1] << 31);
+  r.v[7] = t.v[7] >> 1;
+  return r;
+}
+
 GKR_HD Fr fr_neg(const Fr& a) { return fr_sub(fr_zero(), a); }
 GKR_HD Fr fr_double(const Fr& a) { return fr_add(a, a); }
 

@@ -66,8 +66,10 @@ __device__ __forceinline__ void save_state(DevState* S, const Sha256State& s) {
 }
 
 // The current state as a challenge: rehash with "GKRC" until the 254-bit
-// little-endian value is below p. Each attempt is accepted with probability
-// p / 2^254 > 3/4; the bound on attempts only guarantees termination.
+// little-endian value v is below p. The challenge is v * 2^-256 mod p, so v
+// itself is its Montgomery form: the limbs returned are used as is. Each
+// attempt is accepted with probability p / 2^254 > 3/4; the bound on
+// attempts only guarantees termination.
 __device__ Fr accept(Sha256State& st) {
   Fr c = sha256_to_candidate(st);
   for (int attempt = 0; attempt < 4096 && !fr_is_canonical(c); ++attempt) {
@@ -112,51 +114,35 @@ __device__ void absorb_digest(Sha256State& st, const uint32_t* d) {
 
 __device__ __forceinline__ Fr fr_one_canonical() { return fr_make(1, 0, 0, 0, 0, 0, 0, 0); }
 
-// (1/2) R^2 mod p: the Montgomery product of a Montgomery value x R with it is
-// (x / 2) R^2, the operand that turns a canonical c into the Montgomery form
-// of c x / 2 in one product.
-__device__ __forceinline__ Fr fr_half_r2() {
-  return fr_make(0xcf10b6d4u, 0x2fcd6decu, 0x2e8ae53au, 0x3e19117du, 0xea9e6c71u, 0xa24ce479u, 0x303ff267u,
-                 0x193d8f92u);
-}
-
-// Round message (e0, e1 = claim - e0, e2), run by all 64 lanes of one wave
-// with e0, e2 the same in every lane: write the message to the proof, absorb
-// (e0, e2) with one SHA-256 compression, take the challenge r, store r and move the claim to
-// g(r) = e0 + r (e1 - e0) + r (r - 1) (e2 - 2 e1 + e0) / 2.
-// Independent products run in different lanes. With c the canonical
-// challenge and mont(x, y) = x y / R: before hashing, lanes form canonical
-// e0, e2, e1 and D1 = d1 R^2, D2 = (d2 / 2) R^2; after it, r = mont(c, R^2),
-// r d1 = mont(c, D1), r d2/2 = mont(c, D2) in parallel, then
-// r (r - 1) d2/2 = mont(r d2/2, r - 1): three products on the serial path.
 // The round step on a claim and transcript state held in registers (the
-// same in every lane of the wave): updates both, returns r.
+// same in every lane of the wave): writes the message (e0, e1 = claim - e0,
+// e2, canonical) to the proof, absorbs the Montgomery forms of e0 and e2
+// with one SHA-256 compression, takes the challenge r (whose Montgomery form
+// is the accepted hash value itself), stores r and moves the claim to
+// g(r) = e0 + r (e1 - e0) + r (r - 1) (e2 - 2 e1 + e0) / 2. Independent
+// products run in different lanes: two products on the serial path, both
+// after the hash.
 __device__ __forceinline__ Fr round_step_wave(Fr& claim, Sha256State& state, const Fr& e0, const Fr& e2,
                                               Fr* r_out, uint32_t* msg_out) {
   const int lane = threadIdx.x & 63;
   const Fr e1 = fr_sub(claim, e0);
   const Fr d1 = fr_sub(e1, e0);
-  const Fr d2 = fr_add(fr_sub(e2, fr_double(e1)), e0);
-  // lanes 0..4: canonical e0, e2, e1; D1; D2
-  Fr a = lane == 0 ? e0 : (lane == 1 ? e2 : (lane == 2 ? e1 : (lane == 3 ? d1 : d2)));
-  Fr b = lane < 3 ? fr_one_canonical() : (lane == 3 ? fr_r2() : fr_half_r2());
-  Fr prod = fr_mul(a, b);
-  const Fr c0 = shfl_fr(prod, 0), c2 = shfl_fr(prod, 1), c1 = shfl_fr(prod, 2);
-  const Fr D1 = shfl_fr(prod, 3), D2 = shfl_fr(prod, 4);
-  // absorb: one compression of the block LE(e0) || LE(e2 + 2^254)
+  const Fr d2h = fr_half(fr_add(fr_sub(e2, fr_double(e1)), e0));
   Sha256Block blk;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    blk.w[k] = bswap32(c0.v[k]);
-    blk.w[8 + k] = bswap32(k == 7 ? (c2.v[k] | kRoundMark) : c2.v[k]);
+    blk.w[k] = bswap32(e0.v[k]);
+    blk.w[8 + k] = bswap32(k == 7 ? (e2.v[k] | kRoundMark) : e2.v[k]);
   }
   state = sha256_compress_v(state, blk);
-  const Fr c = accept(state);
-  // lanes 0, 1, 2: r, r d1, r d2/2
-  b = lane == 0 ? fr_r2() : (lane == 1 ? D1 : D2);
-  prod = fr_mul(c, b);
-  const Fr r = shfl_fr(prod, 0), rd1 = shfl_fr(prod, 1), rd2h = shfl_fr(prod, 2);
-  const Fr quad = fr_mul(rd2h, fr_sub(r, fr_one()));
+  const Fr r = accept(state);
+  // lanes 0, 1: r d1, r d2/2
+  Fr prod = fr_mul(r, lane == 0 ? d1 : d2h);
+  const Fr rd1 = shfl_fr(prod, 0), rd2h = shfl_fr(prod, 1);
+  // lanes 0..3: r (r - 1) d2/2, canonical e0, e1, e2
+  const Fr a = lane == 0 ? rd2h : (lane == 1 ? e0 : (lane == 2 ? e1 : e2));
+  prod = fr_mul(a, lane == 0 ? fr_sub(r, fr_one()) : fr_one_canonical());
+  const Fr quad = shfl_fr(prod, 0), c0 = shfl_fr(prod, 1), c1 = shfl_fr(prod, 2), c2 = shfl_fr(prod, 3);
   claim = fr_add(fr_add(e0, rd1), quad);
   if (lane == 0) {
     stf(r_out, 0, r);
@@ -304,7 +290,7 @@ __device__ __forceinline__ void body_squeeze(const Step& st, uint32_t, uint32_t)
   DevState* S = P<DevState*>(st, 0);
   Fr* out = P<Fr*>(st, 1);
   Sha256State sh = load_state(S);
-  for (uint32_t k = 0; k < st.u[0]; ++k) stf(out, k, fr_to_mont(squeeze(sh)));
+  for (uint32_t k = 0; k < st.u[0]; ++k) stf(out, k, squeeze(sh));
   save_state(S, sh);
 }
 
@@ -322,12 +308,12 @@ __device__ __forceinline__ void body_layer_begin(const Step& st, uint32_t, uint3
     return;
   }
   Sha256State sh = load_state(S);
-  const Fr a = fr_to_mont(squeeze(sh));
-  const Fr b = fr_to_mont(squeeze(sh));
+  const Fr a = squeeze(sh);
+  const Fr b = squeeze(sh);
   save_state(S, sh);
   S->alpha = a;
   S->beta = b;
-  S->claim = fr_add(fr_mul(a, vu), fr_mul(b, vv));
+  S->claim = fr_mul_add2(a, vu, b, vv);
 }
 
 // ST_EQ: up to four tables out_j[b] = scale_j * prod_k (bit_k(b) ? r_k : 1 - r_k),

@@ -127,26 +127,28 @@ struct HostTranscript {
       for (int k = 0; k < 8; ++k) w.push_back(bswap32(canon[i].v[k]));
     absorb_words(tag, w.data(), (int)w.size());
   }
-  // The state as a challenge, rehashed with "GKRC" until below p (canonical).
+  // The state as a challenge: rehash with "GKRC" until the 254-bit value v
+  // is below p; the challenge is v * 2^-256 mod p (returned canonical).
   Fr accept() {
     Fr c = sha256_to_candidate(st);
     while (!fr_is_canonical(c)) {
       absorb_words(kTagChallenge, nullptr, 0);
       c = sha256_to_candidate(st);
     }
-    return c;
+    return fr_from_mont(c);
   }
   Fr squeeze() {
     absorb_words(kTagChallenge, nullptr, 0);
     return accept();
   }
   // A round absorbs the values at t = 0 and t = 2 (e1 is fixed by the claim)
-  // with one compression of the block LE(e0) || LE(e2 + 2^254).
+  // with one compression of the block LE(e0 2^256 mod p) || LE(e2 2^256 mod p + 2^254).
   Fr round_challenge(const Fr* e) {
+    const Fr m0 = fr_to_mont(e[0]), m2 = fr_to_mont(e[2]);
     Sha256Block blk;
     for (int k = 0; k < 8; ++k) {
-      blk.w[k] = bswap32(e[0].v[k]);
-      blk.w[8 + k] = bswap32(k == 7 ? (e[2].v[k] | kRoundMark) : e[2].v[k]);
+      blk.w[k] = bswap32(m0.v[k]);
+      blk.w[8 + k] = bswap32(k == 7 ? (m2.v[k] | kRoundMark) : m2.v[k]);
     }
     st = sha256_compress_v(st, blk);
     return accept();

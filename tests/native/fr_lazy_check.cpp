@@ -56,6 +56,7 @@ int main() {
     print(reduce_dyn(A, k));
     print(reduce_dyn(frc_wide(C), k));
     if (k == 2) print(fr_mul_add2(first[0][0], first[0][1], first[1][0], first[1][1]));
+    if (k == 1) print(fr_half(first[0][1]));
   }
   return 0;
 }

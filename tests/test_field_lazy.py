@@ -46,4 +46,7 @@ def test_sums_of_products_single_reduction(checker):
         if len(c) == 2:
             assert int(out[pos], 16) == want
             pos += 1
+        if len(c) == 1:
+            assert int(out[pos], 16) == c[0][1] * pow(2, -1, P) % P  # halving
+            pos += 1
     assert pos == len(out)

@@ -45,7 +45,8 @@ def test_transcript_chain_by_hand():
         cand = int.from_bytes(st, "little") % (1 << 254)
         if cand < F.P:
             break
-    assert v == cand and tr.state == st
+    # the challenge is the accepted value times 2^-256 mod p
+    assert v == cand * pow(2, -256, F.P) % F.P and tr.state == st
 
 
 def _sha256_by_compression(msg: bytes) -> bytes:
@@ -73,12 +74,14 @@ def test_round_challenge_by_hand():
     st = tr.state
     e0, e2 = 12345, F.P - 7
     r = tr.round_challenge(e0, e2)
-    # one compression of the block LE(e0) || LE(e2) with bit 254 of e2 set
-    blk = e0.to_bytes(32, "little") + (e2 + (1 << 254)).to_bytes(32, "little")
+    # one compression of the block LE(e0 2^256 mod p) || LE(e2 2^256 mod p) with bit 254 of the second set
+    R = pow(2, 256, F.P)
+    blk = (e0 * R % F.P).to_bytes(32, "little") + ((e2 * R % F.P) + (1 << 254)).to_bytes(32, "little")
     st = T.compress(st, blk)
     while int.from_bytes(st, "little") % (1 << 254) >= F.P:
         st = hashlib.sha256(st + b"GKRC").digest()
-    assert r == int.from_bytes(st, "little") % (1 << 254) and tr.state == st
+    v = int.from_bytes(st, "little") % (1 << 254)
+    assert r * pow(2, 256, F.P) % F.P == v and tr.state == st
     # the challenge depends on both absorbed values
     t2 = T.Transcript(8)
     assert t2.round_challenge(e0, e2 - 1) != r
