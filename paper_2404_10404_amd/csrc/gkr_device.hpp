@@ -42,6 +42,28 @@ __device__ __forceinline__ Fr shfl_fr(const Fr& a, int src) {
   return r;
 }
 
+// A DPP move of every limb (lanes of rows outside RowMask read zero).
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ Fr dpp_fr(const Fr& a) {
+  Fr r;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) r.v[k] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)a.v[k], Ctrl, RowMask, 0xF, false);
+  return r;
+}
+
+// Sum over the 64 lanes of a wave (all lanes active) into lane 63: DPP steps
+// within quads (quad_perm), half-rows and rows (mirrors), then across rows
+// (row_bcast15, row_bcast31). Other lanes hold partial sums.
+__device__ __forceinline__ Fr wave_sum_to_lane63(Fr v) {
+  v = fr_add(v, dpp_fr<0xB1, 0xF>(v));   // quad_perm [1,0,3,2]
+  v = fr_add(v, dpp_fr<0x4E, 0xF>(v));   // quad_perm [2,3,0,1]
+  v = fr_add(v, dpp_fr<0x141, 0xF>(v));  // row_half_mirror
+  v = fr_add(v, dpp_fr<0x140, 0xF>(v));  // row_mirror
+  v = fr_add(v, dpp_fr<0x142, 0xA>(v));  // row_bcast15 into rows 1 and 3
+  v = fr_add(v, dpp_fr<0x143, 0xC>(v));  // row_bcast31 into rows 2 and 3
+  return v;
+}
+
 template <class T>
 __device__ __forceinline__ T P(const Step& st, int i) {
   return reinterpret_cast<T>(const_cast<void*>(st.p[i]));
@@ -95,12 +117,9 @@ template <int NV>
 __device__ __forceinline__ void block_sum_to_wave0(Fr (&v)[NV]) {
   __shared__ Fr red[NV][16];
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = fr_add(v[k], shfl_xor_fr(v[k], off));
-  }
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum_to_lane63(v[k]);
   const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if (lane == 0) {
+  if (lane == 63) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) red[k][wid] = v[k];
   }
@@ -114,7 +133,6 @@ __device__ __forceinline__ void block_sum_to_wave0(Fr (&v)[NV]) {
     }
   }
 }
-
 // Per-tile partial sums of a grid-wide reduction (written by thread 0).
 template <int NV>
 __device__ void write_partial(Fr (&v)[NV], Fr* partials, uint32_t tile) {
