@@ -24,9 +24,13 @@
  *     caller buffer after a call returns.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Device work is queued asynchronously on that stream; the host
- *     returns as soon as it is queued. No entry point allocates device memory
- *     while proving, synchronises the stream or copies between host and
- *     device, so a whole proof can be captured in a HIP graph.
+ *     returns as soon as it is queued. The proving entry points
+ *     (gkr_prove_circuit, gkr_transcript_init, gkr_output_claim,
+ *     gkr_prove_layer, gkr_plan_reset, gkr_run_batch) allocate no device
+ *     memory, do not synchronise the stream and copy nothing between host and
+ *     device, so a whole proof can be captured in a HIP graph. The set-up and
+ *     convenience calls that do (gkr_circuit_create, gkr_plan_create,
+ *     gkr_plan_progress, gkr_prove_batch) say so below.
  *   - Every entry point returns GKR_OK (0) or a negative status; on failure
  *     gkr_last_error() returns a message for the calling thread. No C++
  *     exception crosses the ABI. Entry points that fail leave caller buffers

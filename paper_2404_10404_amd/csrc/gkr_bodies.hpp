@@ -630,11 +630,8 @@ __device__ __forceinline__ void body_tail(const Step& st, uint32_t, uint32_t) {
     if (size <= 64) {
       // every task is in wave 0: a wave reduction, no workgroup barrier
       if (threadIdx.x < 64) {
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-          acc[0] = fr_add(acc[0], shfl_xor_fr(acc[0], off));
-          acc[1] = fr_add(acc[1], shfl_xor_fr(acc[1], off));
-        }
+        acc[0] = shfl_fr(wave_sum_to_lane63(acc[0]), 63);
+        acc[1] = shfl_fr(wave_sum_to_lane63(acc[1]), 63);
       }
     } else {
       block_sum_to_wave0<2>(acc);
