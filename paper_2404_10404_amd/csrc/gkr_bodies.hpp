@@ -1,7 +1,9 @@
 // Step bodies of the GKR prover kernels (device code, included by the plain
 // kernels and by the persistent batch kernel).
 //
-// Every body runs with 256-thread workgroups (four 64-wide waves). Field
+// Grid-wide bodies run with 256-thread workgroups (four 64-wide waves); the
+// single-workgroup tails take any multiple of 64 threads up to 1024 (512 in
+// the plain kernels, 256 in the batch kernel). Field
 // elements are 32-byte records in Montgomery form, loaded and stored as two
 // 16-byte vectors, so consecutive threads touch consecutive records and every
 // access of a table sweep is coalesced. Gate g = z*2^n + c keeps the copy
@@ -14,10 +16,11 @@
 // steps to resident workgroups.
 //
 // Reductions over a whole table (the round polynomials of the sumcheck) end in
-// the last tile to finish: each tile writes its partial sums, publishes them
-// with a device-scope fence and an atomic counter, and the tile that brings the
-// counter to ntiles adds the partials and runs the Fiat-Shamir step (absorb
-// the message, take the challenge, move the claim) in its first wave.
+// the last tile to finish: each tile writes its partial sums and publishes
+// them with a device-scope release increment of an atomic counter; the tile
+// that brings the counter to ntiles acquires, adds the partials and runs the
+// Fiat-Shamir step (absorb the message, take the challenge, move the claim)
+// in its first wave.
 // Challenges and claims never leave device memory, so a proof is a plain
 // sequence of launches on one stream.
 #pragma once

@@ -22,12 +22,12 @@ constexpr uint32_t kChunkWords = 256;   // 1 KiB SHA-256 leaf chunk of a tree di
 
 // Transcript tags as big-endian words ("GKRD", "GKRV", "GKRC").
 constexpr uint32_t kTagDigest = 0x474B5244u;
+constexpr uint32_t kTagValue = 0x474B5256u;
+constexpr uint32_t kTagChallenge = 0x474B5243u;
 // A round message is absorbed as one compression block holding the
 // Montgomery forms of e0 and e2 (little-endian), with bit 254 of the second
 // (bit 30 of its top limb) set; both are below p < 2^254.
 constexpr uint32_t kRoundMark = 1u << 30;
-constexpr uint32_t kTagValue = 0x474B5256u;
-constexpr uint32_t kTagChallenge = 0x474B5243u;
 
 // Gate-layer wiring on the device. Gate records pack the type into bit 31.
 struct LayerWiring {
