@@ -4,6 +4,7 @@ Usage: python -m paper_2404_10404_amd.build   (or build() from Python)
 """
 import concurrent.futures
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -30,12 +31,32 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def _vgpr_spills(remarks: str):
+    """(kernel, spilled VGPRs) pairs from the compiler's resource-usage remarks."""
+    out, name = [], None
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+        m = re.search(r"VGPRs Spill: (\d+)", line)
+        if m and name:
+            out.append((name, int(m.group(1))))
+    return out
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), "-x", "hip", *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = ["-Rpass-analysis=kernel-resource-usage"] if src.endswith(".hip") else []
+    cmd = [_hipcc(), "-x", "hip", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), res.stdout, res.stderr[-6000:]))
+    # No kernel may spill vector registers to scratch memory: the persistent
+    # batch kernel gave wrong results in stop/resume runs when built with
+    # spills, so a build with spills is refused.
+    spills = [(k, n) for k, n in _vgpr_spills(res.stderr) if n > 0]
+    if spills:
+        raise RuntimeError("%s: kernels spill vector registers: %s" % (src, spills))
     return obj
 
 

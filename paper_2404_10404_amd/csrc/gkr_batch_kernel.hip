@@ -21,7 +21,11 @@ namespace gkr {
 // claimed tile is always run to the end, so a later launch continues exactly
 // where this one stopped. ctl[0] = jobs finished in this launch, ctl[2] =
 // steps completed.
-__global__ void __launch_bounds__(kBlock, 3) k_batch(BatchArgs a) {
+// The launch bound (two workgroups per CU, up to 256 vector registers per
+// lane) keeps every value of this large kernel in registers: builds that
+// spilled vector registers to scratch memory gave wrong proofs in runs that
+// stop and resume, and the build refuses spills.
+__global__ void __launch_bounds__(kBlock, 2) k_batch(BatchArgs a) {
   __shared__ uint32_t sh_job, sh_step, sh_tile, sh_state;  // state: 0 work, 1 none, 2 exit
   __shared__ Step sh_st;
   uint32_t* ctl = a.ctl;
@@ -77,9 +81,13 @@ __global__ void __launch_bounds__(kBlock, 3) k_batch(BatchArgs a) {
     if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __syncthreads();
     run_step_tile(sh_st, tile, sh_st.ntiles);
+    // release this tile's writes before it is counted done (workgroups on
+    // other XCDs read these tables in the next step): every wave waits for its
+    // own stores to complete, then one wave writes the L2 back
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // release this tile's writes
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       uint32_t* ctr = jb.ctr;
       const uint32_t d = atomicAdd(&ctr[1 + jb.nsteps + s], 1u);
       if (d == sh_st.ntiles - 1) {

@@ -2,8 +2,8 @@
 // kernels and by the persistent batch kernel).
 //
 // Grid-wide bodies run with 256-thread workgroups (four 64-wide waves); the
-// single-workgroup tails take any multiple of 64 threads up to 1024 (512 in
-// the plain kernels, 256 in the batch kernel). Field
+// single-workgroup tails take any multiple of 64 threads from 128 to 1024
+// (512 in the plain kernels, 256 in the batch kernel). Field
 // elements are 32-byte records in Montgomery form, loaded and stored as two
 // 16-byte vectors, so consecutive threads touch consecutive records and every
 // access of a table sweep is coalesced. Gate g = z*2^n + c keeps the copy
@@ -117,20 +117,22 @@ __device__ void absorb_digest(Sha256State& st, const uint32_t* d) {
 
 __device__ __forceinline__ Fr fr_one_canonical() { return fr_make(1, 0, 0, 0, 0, 0, 0, 0); }
 
-// The round step on a claim and transcript state held in registers (the
-// same in every lane of the wave): writes the message (e0, e1 = claim - e0,
-// e2, canonical) to the proof, absorbs the Montgomery forms of e0 and e2
-// with one SHA-256 compression, takes the challenge r (whose Montgomery form
-// is the accepted hash value itself), stores r and moves the claim to
-// g(r) = e0 + r (e1 - e0) + r (r - 1) (e2 - 2 e1 + e0) / 2. Independent
-// products run in different lanes: two products on the serial path, both
-// after the hash.
-__device__ __forceinline__ Fr round_step_wave(Fr& claim, Sha256State& state, const Fr& e0, const Fr& e2,
-                                              Fr* r_out, uint32_t* msg_out) {
-  const int lane = threadIdx.x & 63;
-  const Fr e1 = fr_sub(claim, e0);
-  const Fr d1 = fr_sub(e1, e0);
-  const Fr d2h = fr_half(fr_add(fr_sub(e2, fr_double(e1)), e0));
+// The value of lane `src` (a constant) in every lane of the wave.
+__device__ __forceinline__ Fr lane_fr(const Fr& a, int src) {
+  Fr r;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) r.v[k] = (uint32_t)__builtin_amdgcn_readlane((int)a.v[k], src);
+  return r;
+}
+
+// The transcript half of a round on a claim and transcript state held in
+// registers (the same in every lane of the wave): e1 = claim - e0, then one
+// SHA-256 compression absorbs the Montgomery forms of e0 and e2, and the
+// accepted hash value is the challenge r in Montgomery form. Only additions
+// precede the hash.
+__device__ __forceinline__ Fr round_hash_wave(const Fr& claim, Sha256State& state, const Fr& e0, const Fr& e2,
+                                              Fr& e1) {
+  e1 = fr_sub(claim, e0);
   Sha256Block blk;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -138,38 +140,25 @@ __device__ __forceinline__ Fr round_step_wave(Fr& claim, Sha256State& state, con
     blk.w[8 + k] = bswap32(k == 7 ? (e2.v[k] | kRoundMark) : e2.v[k]);
   }
   state = sha256_compress_v(state, blk);
-  const Fr r = accept(state);
-  // lanes 0, 1: r d1, r d2/2
-  Fr prod = fr_mul(r, lane == 0 ? d1 : d2h);
-  const Fr rd1 = shfl_fr(prod, 0), rd2h = shfl_fr(prod, 1);
-  // lanes 0..3: r (r - 1) d2/2, canonical e0, e1, e2
-  const Fr a = lane == 0 ? rd2h : (lane == 1 ? e0 : (lane == 2 ? e1 : e2));
-  prod = fr_mul(a, lane == 0 ? fr_sub(r, fr_one()) : fr_one_canonical());
-  const Fr quad = shfl_fr(prod, 0), c0 = shfl_fr(prod, 1), c1 = shfl_fr(prod, 2), c2 = shfl_fr(prod, 3);
-  claim = fr_add(fr_add(e0, rd1), quad);
-  if (lane == 0) {
-    stf(r_out, 0, r);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      msg_out[k] = c0.v[k];
-      msg_out[8 + k] = c1.v[k];
-      msg_out[16 + k] = c2.v[k];
-    }
-  }
-  return r;
+  return accept(state);
 }
 
-// The round step with the claim and state in the proof's device state.
-__device__ Fr finish_round_wave(DevState* S, const Fr& e0, const Fr& e2, Fr* r_out,
-                                uint32_t* msg_out) {
-  Fr claim = S->claim;
-  Sha256State st = load_state(S);
-  const Fr r = round_step_wave(claim, st, e0, e2, r_out, msg_out);
-  if ((threadIdx.x & 63) == 0) {
-    save_state(S, st);
-    S->claim = claim;
-  }
-  return r;
+// The product half: the next claim g(r) = e0 + r (e1 - e0) + r (r - 1)
+// (e2 - 2 e1 + e0) / 2, evaluated as e0 + r (A + r B) with B = (e2 - 2 e1 +
+// e0) / 2 and A = e1 - e0 - B, and the message (e0, e1, e2, canonical) stored
+// by lanes 1..3 (one element each) to msg_out. The products run in different
+// lanes: two rounds of products, both in every lane of the wave.
+__device__ __forceinline__ Fr round_claim_wave(const Fr& r, const Fr& e0, const Fr& e1, const Fr& e2,
+                                               uint32_t* msg_out) {
+  const int lane = threadIdx.x & 63;
+  const Fr B = fr_half(fr_add(fr_sub(e2, fr_double(e1)), e0));
+  const Fr A = fr_sub(fr_sub(e1, e0), B);
+  // lane 0: r B; lanes 1..3: canonical e0, e1, e2
+  const Fr a = lane == 0 ? r : (lane == 1 ? e0 : (lane == 2 ? e1 : e2));
+  const Fr prod = fr_mul(a, lane == 0 ? B : fr_one_canonical());
+  if (lane >= 1 && lane <= 3) stf(reinterpret_cast<Fr*>(msg_out), lane - 1, prod);
+  const Fr t = fr_mul(r, fr_add(A, lane_fr(prod, 0)));
+  return fr_add(e0, t);
 }
 
 // A phase's final value (one thread): store it, write it to the proof and absorb it.
@@ -272,7 +261,8 @@ __device__ __forceinline__ void body_digest(const Step& st, uint32_t tile, uint3
 }
 
 // ST_TRANSCRIPT_BEGIN: st = seed state (w0..7), then absorb the circuit digest
-// (w8..15) and the two vector digests; also zeroes the reduction counter.
+// (w8..15) and the two vector digests; also zeroes the reduction counter and
+// clears the pending round.
 // p0 S, p1 dig_in, p2 dig_out.
 __device__ __forceinline__ void body_transcript_begin(const Step& st, uint32_t, uint32_t) {
   if (threadIdx.x != 0) return;
@@ -285,6 +275,7 @@ __device__ __forceinline__ void body_transcript_begin(const Step& st, uint32_t, 
   absorb_digest(sh, P<const uint32_t*>(st, 2));
   save_state(S, sh);
   S->counter = 0;
+  S->pending = 0;
 }
 
 // ST_SQUEEZE: u0 challenges into p1 (Montgomery form). p0 S.
@@ -432,12 +423,46 @@ __device__ __forceinline__ void body_p1_init_round(const Step& st, uint32_t tile
   write_partial<2>(acc, P<Fr*>(st, 10), tile);
 }
 
-// Sum of the partials, then the Fiat-Shamir step in wave 0.
+// Sum of the partials, then the round's transcript step in wave 0: the hash
+// of (e0, e2) gives r, and the round becomes the pending one. Meanwhile wave 1
+// moves the claim through the previous pending round (if any) and writes that
+// round's message, so the products by r stay off the chain of hashes.
 __device__ __forceinline__ void finish_reduced_round(const Fr* partials, uint32_t ntiles, DevState* S, Fr* r_out,
                                      uint32_t* msg) {
   Fr tot[2];
   sum_partials<2>(partials, ntiles, tot);
-  if (threadIdx.x < 64) finish_round_wave(S, tot[0], tot[1], r_out, msg);
+  const uint32_t wid = threadIdx.x >> 6;
+  bool pend = false;
+  Fr claim, pe0, pe2, pr;
+  uint32_t* pmsg = nullptr;
+  if (wid == 1) {
+    pend = S->pending != 0;
+    if (pend) {
+      claim = S->claim;
+      pe0 = S->pend_e0;
+      pe2 = S->pend_e2;
+      pr = S->pend_r;
+      pmsg = S->pend_msg;
+    }
+  }
+  __syncthreads();
+  if (wid == 0) {
+    Sha256State st = load_state(S);
+    Fr e1_unused;
+    const Fr r = round_hash_wave(fr_zero(), st, tot[0], tot[1], e1_unused);
+    if (threadIdx.x == 0) {
+      save_state(S, st);
+      stf(r_out, 0, r);
+      S->pend_e0 = tot[0];
+      S->pend_e2 = tot[1];
+      S->pend_r = r;
+      S->pend_msg = msg;
+      S->pending = 1;
+    }
+  } else if (wid == 1 && pend) {
+    claim = round_claim_wave(pr, pe0, fr_sub(claim, pe0), pe2, pmsg);
+    if (threadIdx.x == 64) S->claim = claim;
+  }
 }
 
 __device__ __forceinline__ void finish_p1_init_round(const Step& st, uint32_t ntiles) {
@@ -552,15 +577,24 @@ __device__ __forceinline__ T pick(T const (&a)[NT], uint32_t k) {
   return p;
 }
 
-// ST_TAIL_A / ST_TAIL_B: the remaining u0 rounds of a phase in one workgroup,
-// then the final fold. q0 = table size before the pending fold (if any).
-// Pointers: src, dst, rpending, S, r_out, msg, final_out, proof_value. The
-// final value of table 0 is stored in *final_out and, if proof_value is not
-// null, written to the proof and absorbed.
-// Each round runs in two stages over all threads of the workgroup, so that the
-// independent products of a round are spread over every wave: the fold by the
-// pending challenge (one task per table entry, in place after the first
-// round), then the evaluation at t = 0 and t = 2 (one task per pair and t).
+// ST_TAIL_A / ST_TAIL_B: the remaining u0 rounds of a phase in one workgroup
+// (at least 128 threads), then the final fold. q0 = table size before the
+// pending fold (if any). Pointers: src, dst, rpending, S, r_out, msg,
+// final_out, proof_value. The final value of table 0 is stored in *final_out
+// and, if proof_value is not null, written to the proof and absorbed.
+// The transcript chain of the rounds needs only the sums e0 and e2 of each
+// round (the hash absorbs them; the challenge is the hash value), not the
+// running claim, so the two chains run in different waves:
+//  - wave 0 holds the transcript state and hashes each round's e0, e2 as soon
+//    as the sums are in, then publishes r;
+//  - wave 1 holds the claim: while wave 0 hashes round j, it moves the claim
+//    through round j - 1 (e1 = claim - e0, products by r) and writes that
+//    round's message (in round 0, through the round a grid finisher left
+//    pending, if any); the last round's claim moves after the final fold, and
+//    nothing is left pending;
+//  - waves 1.. (the workers) fold the tables by the previous challenge (one
+//    task per entry, in place after the first round) and evaluate them at
+//    t = 0 and t = 2 (one task per pair and t).
 template <class Form>
 __device__ __forceinline__ void body_tail(const Step& st, uint32_t, uint32_t) {
   constexpr int NT = Form::NT;
@@ -577,34 +611,45 @@ __device__ __forceinline__ void body_tail(const Step& st, uint32_t, uint32_t) {
   uint32_t* msg = P<uint32_t*>(st, 2 * NT + 3);
   Fr* final_out = P<Fr*>(st, 2 * NT + 4);
   uint32_t* proof_value = P<uint32_t*>(st, 2 * NT + 5);
-  const uint32_t nthr = blockDim.x;
+  const uint32_t wid = threadIdx.x >> 6;
+  const uint32_t w = threadIdx.x - 64, nw = blockDim.x - 64;  // worker index and count
   uint64_t size = st.q[0];
   const uint32_t rounds = st.u[0];
-  __shared__ Fr r_sh;
+  __shared__ Fr r_sh, e_sh[2];  // the last round's challenge and sums (e0, e2)
+  __shared__ Fr red1[2];
   bool fold = rpending != nullptr;
-  // the running claim and transcript state stay in wave 0's registers for the
-  // whole tail and go back to the device state at its end
-  Fr claim = fr_zero();
-  Sha256State state;
-  if (threadIdx.x < 64) {
+  Sha256State state;  // wave 0
+  // wave 1: the claim and the pending round it has not moved through yet
+  Fr claim = fr_zero(), pe0 = fr_zero(), pe2 = fr_zero(), pr = fr_zero();
+  uint32_t* pmsg = nullptr;
+  bool pend = false;
+  if (wid == 0) state = load_state(S);
+  if (wid == 1) {
     claim = S->claim;
-    state = load_state(S);
+    pend = S->pending != 0;
+    if (pend) {
+      pe0 = S->pend_e0;
+      pe2 = S->pend_e2;
+      pr = S->pend_r;
+      pmsg = S->pend_msg;
+    }
   }
-  __syncthreads();
   if (threadIdx.x == 0) r_sh = fold ? ldf(rpending, 0) : fr_zero();
   __syncthreads();
   for (uint32_t j = 0;; ++j) {
     if (fold) {
-      // fold: entry i of table k becomes src[i] + r (src[i + m] - src[i])
       const uint64_t m = size / 2;
-      const uint32_t lg = 63 - __clzll(m);
-      const Fr r = r_sh;
-      for (uint64_t t = threadIdx.x; t < NT * m; t += nthr) {
-        const uint32_t k = (uint32_t)(t >> lg);
-        const uint64_t i = t & (m - 1);
-        const Fr* s = pick<NT>(src, k);
-        const Fr a0 = ldf(s, i), a1 = ldf(s, i + m);
-        stf(pick<NT>(dst, k), i, fr_add(a0, fr_mul(r, fr_sub(a1, a0))));
+      if (wid > 0) {
+        // entry i of table k becomes src[i] + r (src[i + m] - src[i])
+        const uint32_t lg = 63 - __clzll(m);
+        const Fr rf = r_sh;
+        for (uint64_t t = w; t < NT * m; t += nw) {
+          const uint32_t k = (uint32_t)(t >> lg);
+          const uint64_t i = t & (m - 1);
+          const Fr* sp = pick<NT>(src, k);
+          const Fr a0 = ldf(sp, i), a1 = ldf(sp, i + m);
+          stf(pick<NT>(dst, k), i, fr_add(a0, fr_mul(rf, fr_sub(a1, a0))));
+        }
       }
       __syncthreads();
 #pragma unroll
@@ -615,42 +660,82 @@ __device__ __forceinline__ void body_tail(const Step& st, uint32_t, uint32_t) {
     // evaluate: task u < size is the pair b = u mod half at t = 0 (u < half) or t = 2
     const uint64_t half = size / 2;
     Fr acc[2] = {fr_zero(), fr_zero()};
-    for (uint64_t u = threadIdx.x; u < size; u += nthr) {
-      const bool t2 = u >= half;
-      const uint64_t b = t2 ? u - half : u;
-      Fr x[NT];
+    if (wid > 0) {
+      for (uint64_t u = w; u < size; u += nw) {
+        const bool t2 = u >= half;
+        const uint64_t b = t2 ? u - half : u;
+        Fr x[NT];
 #pragma unroll
-      for (int k = 0; k < NT; ++k) {
-        const Fr lo = ldf(src[k], b), hi = ldf(src[k], b + half);
-        x[k] = t2 ? fr_sub(fr_double(hi), lo) : lo;
+        for (int k = 0; k < NT; ++k) {
+          const Fr lo = ldf(src[k], b), hi = ldf(src[k], b + half);
+          x[k] = t2 ? fr_sub(fr_double(hi), lo) : lo;
+        }
+        Fr v;
+        if constexpr (NT == 3) v = fr_add(fr_mul(x[0], x[1]), x[2]);
+        else v = fr_add(fr_mul_add2(x[0], x[1], x[2], x[3]), x[4]);
+        if (t2) acc[1] = fr_add(acc[1], v);
+        else acc[0] = fr_add(acc[0], v);
       }
-      Fr v;
-      if constexpr (NT == 3) v = fr_add(fr_mul(x[0], x[1]), x[2]);
-      else v = fr_add(fr_mul_add2(x[0], x[1], x[2], x[3]), x[4]);
-      if (t2) acc[1] = fr_add(acc[1], v);
-      else acc[0] = fr_add(acc[0], v);
+    }
+    // the claim wave takes the previous round's sums and challenge
+    if (wid == 1 && j > 0) {
+      pe0 = e_sh[0];
+      pe2 = e_sh[1];
+      pr = r_sh;
+      pmsg = msg + 24 * (j - 1);
+      pend = true;
     }
     if (size <= 64) {
-      // every task is in wave 0: a wave reduction, no workgroup barrier
-      if (threadIdx.x < 64) {
-        acc[0] = shfl_fr(wave_sum_to_lane63(acc[0]), 63);
-        acc[1] = shfl_fr(wave_sum_to_lane63(acc[1]), 63);
+      // every task is in the first worker wave
+      if (wid == 1) {
+        acc[0] = wave_sum_to_lane63(acc[0]);
+        acc[1] = wave_sum_to_lane63(acc[1]);
+        if (threadIdx.x == 127) {
+          red1[0] = acc[0];
+          red1[1] = acc[1];
+        }
+      }
+      __syncthreads();
+      if (wid == 0) {
+        acc[0] = red1[0];
+        acc[1] = red1[1];
       }
     } else {
       block_sum_to_wave0<2>(acc);
     }
-    if (threadIdx.x < 64) {
-      const Fr r = round_step_wave(claim, state, acc[0], acc[1], r_out + j, msg + 24 * j);
-      if (threadIdx.x == 0) r_sh = r;
+    if (wid == 0) {
+      Fr e1_unused;
+      const Fr r = round_hash_wave(fr_zero(), state, acc[0], acc[1], e1_unused);
+      if (threadIdx.x == 0) {
+        r_sh = r;
+        e_sh[0] = acc[0];
+        e_sh[1] = acc[1];
+        stf(r_out, j, r);
+      }
+    } else if (wid == 1 && pend) {
+      claim = round_claim_wave(pr, pe0, fr_sub(claim, pe0), pe2, pmsg);
+      pend = false;
     }
     __syncthreads();
     fold = true;
   }
-  if (threadIdx.x == 0) {
+  // the last round's claim move (the final fold has run)
+  if (wid == 1) {
     if (rounds > 0) {
-      save_state(S, state);
-      S->claim = claim;
+      pe0 = e_sh[0];
+      pe2 = e_sh[1];
+      pr = r_sh;
+      pmsg = msg + 24 * (rounds - 1);
+      pend = true;
     }
+    if (pend) claim = round_claim_wave(pr, pe0, fr_sub(claim, pe0), pe2, pmsg);
+    if (threadIdx.x == 64) {
+      S->claim = claim;
+      S->pending = 0;
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (rounds > 0) save_state(S, state);
     const Fr v = ldf(src[0], 0);
     if (proof_value) finish_value(S, v, final_out, proof_value);
     else *final_out = v;
@@ -881,7 +966,10 @@ __device__ __forceinline__ void body_state_import(const Step& st, uint32_t, uint
     const uint8_t* b = in + 4 * threadIdx.x;
     S->st[threadIdx.x] = ((uint32_t)b[0] << 24) | ((uint32_t)b[1] << 16) | ((uint32_t)b[2] << 8) | b[3];
   }
-  if (threadIdx.x == 0) S->counter = 0;
+  if (threadIdx.x == 0) {
+    S->counter = 0;
+    S->pending = 0;
+  }
 }
 
 #undef GTID

@@ -42,8 +42,12 @@ struct LayerWiring {
 struct DevState {
   uint32_t st[8];   // transcript chaining value, SHA-256 words h[0..7]
   uint32_t counter; // last-workgroup counter of grid reductions (returns to 0)
-  uint32_t pad[7];
-  Fr claim;         // running sumcheck claim
+  uint32_t pending; // 1: the claim has not yet moved through the last round
+  uint32_t pad1;
+  uint32_t* pend_msg;  // where that round's message goes
+  uint32_t pad[3];
+  Fr claim;         // running sumcheck claim (before the pending round, if any)
+  Fr pend_e0, pend_e2, pend_r;  // the pending round: its sums at t = 0, 2 and its challenge
   Fr alpha, beta;
   Fr vx, vy;
   Fr su, sv;        // sum_c U[c], sum_c V[c]

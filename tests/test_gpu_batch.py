@@ -167,3 +167,35 @@ def test_graph_captured_proof_replays_bit_exact(gkr):
         gkr.prove_circuit(b.c, b.d_in, b.spec.seed, b.out, b.proof, b.ws)
         torch.cuda.synchronize()
         assert b.proof_bytes() == want_b, rep
+
+
+def test_large_jobs_in_one_persistent_launch_match_plain_and_verify(gkr):
+    """The 16 largest jobs of the serving mix (up to 2^22 gates per layer, 2^5..2^10
+    copies) in one persistent launch: each step has hundreds of tiles spread over
+    every XCD, and the next step's tiles read the tables they wrote. Every proof
+    and output vector equals the plain launch's for the same job, and the host
+    verifier accepts it. (A tile that published its writes before all of its
+    waves' stores had reached the L2 gave wrong proofs for some of these jobs.)"""
+    import torch
+    specs = gs.serving_jobs_c5(96)
+    big = sorted(range(len(specs)), key=lambda k: (-specs[k].gate_layers, k))[:16]
+    _log("batch: building the 16 largest serving jobs %s" % big)
+    jobs = [_Job(gkr, specs[k]) for k in big]
+    plans = [gkr.Plan(j.job) for j in jobs]
+    ctl = torch.zeros(4, dtype=torch.int32, device="cuda")
+    _log("batch: one persistent launch over %d jobs" % len(jobs))
+    gkr.run_batch(plans, ctl)
+    torch.cuda.synchronize()
+    assert int(ctl[0]) == len(jobs)
+    for k, j in zip(big, jobs):
+        batched = j.proof_bytes()
+        outs = np.ascontiguousarray(gkr.host_elements(j.out)).copy()
+        j.out.zero_()
+        j.proof.zero_()
+        gkr.prove_circuit(j.c, j.d_in, j.spec.seed, j.out, j.proof, j.ws)
+        torch.cuda.synchronize()
+        assert j.proof_bytes() == batched, (k, j.spec)
+        assert np.array_equal(gkr.host_elements(j.out), outs), (k, j.spec)
+        assert gkr.verify(j.c, j.inputs, outs, j.spec.seed, batched) == 1, (k, j.spec)
+    for p in plans:
+        p.close()

@@ -52,3 +52,28 @@ def test_results_identical_alone_and_in_the_mix(executor):
     s = serve.summary(mixed, reqs)
     assert s["jobs"] == len(reqs) and s["p99_latency_s"] >= s["p50_latency_s"]
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("executor", ["streams", "persistent"])
+def test_serving_mix_of_96_matches_plain(executor):
+    """The 96-job serving mix (2^12..2^22 gates per layer, depth 8..24), all queued at
+    once: up to 32 jobs run together, and the persistent executor's launches end
+    whenever a job finishes, so a job's steps are split over many launches while
+    other jobs join. Every proof and output vector equals the plain loop's."""
+    import torch
+
+    from paper_2404_10404_amd import gkr, serve
+    specs = gs.serving_jobs_c5(96)
+    reqs = []
+    for k, spec in enumerate(specs):
+        c = gkr.Circuit.from_synth(spec, gs.make_wiring(spec))
+        reqs.append(serve.Request(rid=k, circuit=c, inputs=gs.make_inputs(spec), seed=spec.seed, arrival=0.0,
+                                  gate_layers=spec.gate_layers))
+    _log("serving mix: the plain loop over %d jobs" % len(reqs))
+    alone = serve.serve_plain(reqs)
+    _log("serving mix: continuous batching (%s)" % executor)
+    ex = serve.StreamExecutor() if executor == "streams" else serve.GpuExecutor()
+    mixed = serve.serve(reqs, ex, max_slots=32, budget_bytes=96 << 30)
+    torch.cuda.synchronize()
+    wrong = [k for k in range(len(reqs)) if mixed[k].proof != alone[k].proof or mixed[k].outputs != alone[k].outputs]
+    assert not wrong, wrong
