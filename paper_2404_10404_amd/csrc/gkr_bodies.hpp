@@ -686,14 +686,20 @@ __device__ __forceinline__ void body_tail(const Step& st, uint32_t, uint32_t) {
       pend = true;
     }
     if (size <= 64) {
-      // every task is in the first worker wave
+      // Every task is in the first worker wave, one per lane: lanes [0, half)
+      // hold the t = 0 terms and lanes [half, size) the t = 2 terms, so one
+      // segmented sum over aligned blocks of `half` lanes (log2(half) DPP
+      // steps) leaves e0 in lane half - 1 and e2 in lane size - 1.
       if (wid == 1) {
-        acc[0] = wave_sum_to_lane63(acc[0]);
-        acc[1] = wave_sum_to_lane63(acc[1]);
-        if (threadIdx.x == 127) {
-          red1[0] = acc[0];
-          red1[1] = acc[1];
-        }
+        Fr v = fr_add(acc[0], acc[1]);
+        if (half >= 2) v = fr_add(v, dpp_fr<0xB1, 0xF>(v));   // quad_perm [1,0,3,2]
+        if (half >= 4) v = fr_add(v, dpp_fr<0x4E, 0xF>(v));   // quad_perm [2,3,0,1]
+        if (half >= 8) v = fr_add(v, dpp_fr<0x141, 0xF>(v));  // row_half_mirror
+        if (half >= 16) v = fr_add(v, dpp_fr<0x140, 0xF>(v)); // row_mirror
+        if (half >= 32) v = fr_add(v, dpp_fr<0x142, 0xA>(v)); // row_bcast15 into rows 1 and 3
+        const uint32_t lane = threadIdx.x & 63;
+        if (lane == half - 1) red1[0] = v;
+        if (lane == size - 1) red1[1] = v;
       }
       __syncthreads();
       if (wid == 0) {
