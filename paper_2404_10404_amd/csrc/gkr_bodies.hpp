@@ -153,9 +153,18 @@ __device__ __forceinline__ Fr round_claim_wave(const Fr& r, const Fr& e0, const 
   const int lane = threadIdx.x & 63;
   const Fr B = fr_half(fr_add(fr_sub(e2, fr_double(e1)), e0));
   const Fr A = fr_sub(fr_sub(e1, e0), B);
-  // lane 0: r B; lanes 1..3: canonical e0, e1, e2
-  const Fr a = lane == 0 ? r : (lane == 1 ? e0 : (lane == 2 ? e1 : e2));
-  const Fr prod = fr_mul(a, lane == 0 ? B : fr_one_canonical());
+  // lane 0: r B; lanes 1..3: canonical e0, e1, e2 (register selects over
+  // opaque candidates: no private array for the optimizer to index)
+  Fr c1 = e0, c2 = e1, c3 = e2, one = fr_one_canonical();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) asm volatile("" : "+v"(c1.v[k]), "+v"(c2.v[k]), "+v"(c3.v[k]), "+v"(one.v[k]));
+  Fr a = r, b = B;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    a.v[k] = lane == 1 ? c1.v[k] : (lane == 2 ? c2.v[k] : (lane == 3 ? c3.v[k] : a.v[k]));
+    b.v[k] = lane == 0 ? b.v[k] : one.v[k];
+  }
+  const Fr prod = fr_mul(a, b);
   if (lane >= 1 && lane <= 3) stf(reinterpret_cast<Fr*>(msg_out), lane - 1, prod);
   const Fr t = fr_mul(r, fr_add(A, lane_fr(prod, 0)));
   return fr_add(e0, t);
@@ -567,14 +576,21 @@ __device__ __forceinline__ void finish_round_step(const Step& st, uint32_t ntile
                        P<uint32_t*>(st, R::kMsg));
 }
 
-// Table k of NT pointers, for a k that varies across lanes (selects, no
-// indexed private array).
+// Table k of NT pointers, for a k that varies across lanes: a chain of
+// register selects. Each candidate passes through an empty asm statement, so
+// the optimizer cannot turn the chain back into an indexed load from a
+// private array (which would put the pointers in scratch memory and add a
+// dependent load to every task).
 template <int NT, class T>
 __device__ __forceinline__ T pick(T const (&a)[NT], uint32_t k) {
-  T p = a[0];
+  uint64_t p = reinterpret_cast<uint64_t>(a[0]);
 #pragma unroll
-  for (int q = 1; q < NT; ++q) p = k == (uint32_t)q ? a[q] : p;
-  return p;
+  for (int q = 1; q < NT; ++q) {
+    uint64_t c = reinterpret_cast<uint64_t>(a[q]);
+    asm volatile("" : "+v"(c));
+    p = k == (uint32_t)q ? c : p;
+  }
+  return reinterpret_cast<T>(p);
 }
 
 // ST_TAIL_A / ST_TAIL_B: the remaining u0 rounds of a phase in one workgroup
