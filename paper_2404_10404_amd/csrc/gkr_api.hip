@@ -102,8 +102,9 @@ size_t plan_workspace(const gkr_circuit& c, Plan& p) {
   p.off_Wc = take(E << n);
   p.off_Fc = take(E << n);
   p.off_Kc = take(E << n);
-  // row split of the copy-table pass: about 2^20 threads in total (a power of two)
-  uint64_t want = (n >= 20) ? 1 : (1ull << (20 - n));
+  // row split of the copy-table pass: about 2^18 threads in total (a power of
+  // two), so each thread contracts several rows before its partial is stored
+  uint64_t want = (n >= 18) ? 1 : (1ull << (18 - n));
   uint64_t rows = 1ull << sigp_max;
   p.ychunks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, std::min<uint64_t>(rows, 1ull << 15)));
   p.off_wpart = take(E * ((size_t)p.ychunks << n));
