@@ -19,8 +19,9 @@
 // the last tile to finish: each tile writes its partial sums and publishes
 // them with a device-scope release increment of an atomic counter; the tile
 // that brings the counter to ntiles acquires, adds the partials and runs the
-// Fiat-Shamir step (absorb the message, take the challenge, move the claim)
-// in its first wave.
+// round's Fiat-Shamir step: its first wave hashes the sums and takes the
+// challenge, its second wave moves the claim through the previous round
+// (the products by r stay off the chain of hashes).
 // Challenges and claims never leave device memory, so a proof is a plain
 // sequence of launches on one stream.
 #pragma once
@@ -125,14 +126,12 @@ __device__ __forceinline__ Fr lane_fr(const Fr& a, int src) {
   return r;
 }
 
-// The transcript half of a round on a claim and transcript state held in
-// registers (the same in every lane of the wave): e1 = claim - e0, then one
-// SHA-256 compression absorbs the Montgomery forms of e0 and e2, and the
-// accepted hash value is the challenge r in Montgomery form. Only additions
-// precede the hash.
-__device__ __forceinline__ Fr round_hash_wave(const Fr& claim, Sha256State& state, const Fr& e0, const Fr& e2,
-                                              Fr& e1) {
-  e1 = fr_sub(claim, e0);
+// The transcript half of a round, on a transcript state held in registers
+// (the same in every lane of the wave): one SHA-256 compression absorbs the
+// Montgomery forms of the round's sums e0 and e2, and the accepted hash value
+// is the challenge r in Montgomery form. No product precedes the hash, and
+// the running claim is not needed (e1 enters only the message).
+__device__ __forceinline__ Fr round_hash_wave(Sha256State& state, const Fr& e0, const Fr& e2) {
   Sha256Block blk;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -457,8 +456,7 @@ __device__ __forceinline__ void finish_reduced_round(const Fr* partials, uint32_
   __syncthreads();
   if (wid == 0) {
     Sha256State st = load_state(S);
-    Fr e1_unused;
-    const Fr r = round_hash_wave(fr_zero(), st, tot[0], tot[1], e1_unused);
+    const Fr r = round_hash_wave(st, tot[0], tot[1]);
     if (threadIdx.x == 0) {
       save_state(S, st);
       stf(r_out, 0, r);
@@ -726,8 +724,7 @@ __device__ __forceinline__ void body_tail(const Step& st, uint32_t, uint32_t) {
       block_sum_to_wave0<2>(acc);
     }
     if (wid == 0) {
-      Fr e1_unused;
-      const Fr r = round_hash_wave(fr_zero(), state, acc[0], acc[1], e1_unused);
+      const Fr r = round_hash_wave(state, acc[0], acc[1]);
       if (threadIdx.x == 0) {
         r_sh = r;
         e_sh[0] = acc[0];
