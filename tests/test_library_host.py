@@ -118,3 +118,18 @@ def test_tuning_round_trip_and_ranges():
             assert gkr.get_tuning() == (9, 512, 2)  # a rejected setting changes nothing
     finally:
         gkr.set_tuning(*old)
+
+
+def test_build_refuses_register_spills():
+    """The build reads the compiler's resource-usage remarks and refuses a
+    kernel that spills vector registers to scratch memory."""
+    from paper_2404_10404_amd import build
+    remarks = "\n".join([
+        "x.hip:24:1: remark: Function Name: _ZN3gkr7k_batchENS_9BatchArgsE [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:24:1: remark:     VGPRs: 240 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:24:1: remark:     VGPRs Spill: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:99:1: remark: Function Name: _ZN3gkr8k_tail_aENS_4StepE [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:99:1: remark:     VGPRs Spill: 3 [-Rpass-analysis=kernel-resource-usage]",
+    ])
+    assert build._vgpr_spills(remarks) == [("_ZN3gkr7k_batchENS_9BatchArgsE", 0), ("_ZN3gkr8k_tail_aENS_4StepE", 3)]
+    assert build._vgpr_spills("no remarks here") == []
