@@ -291,7 +291,7 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=96.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build proves one worker's share on a single MI355X "
+        print("bench.py measures one GPU: the prover proves one worker's share on a single MI355X "
               "and has no multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
