@@ -199,3 +199,34 @@ def test_large_jobs_in_one_persistent_launch_match_plain_and_verify(gkr):
         assert gkr.verify(j.c, j.inputs, outs, j.spec.seed, batched) == 1, (k, j.spec)
     for p in plans:
         p.close()
+
+
+@pytest.mark.parametrize("tun", [(1, 4, 1), (2, 1, 1), (16, 64, 2)], ids=["grid-rounds", "one-tile-rounds", "tails"])
+def test_batch_schedules_with_stops_match_oracle(gkr, tun):
+    """Plans recorded under extreme schedules (nearly every round a grid round,
+    each leaving its claim move pending for the next step; or whole phases in
+    tails), run in short launches that stop after a few steps: every round's
+    pending claim move crosses launch boundaries, and the proofs stay the
+    oracle's."""
+    import torch
+    old = gkr.get_tuning()
+    try:
+        gkr.set_tuning(*tun)
+        jobs = _mix(gkr)
+        plans = [gkr.Plan(j.job) for j in jobs]
+    finally:
+        gkr.set_tuning(*old)
+    ctl = torch.zeros(4, dtype=torch.int32, device="cuda")
+    _log("batch: schedule %s, launches of at most 7 steps" % (tun,))
+    launches = 0
+    while launches < 5000:
+        gkr.run_batch(plans, ctl, step_budget=7)
+        torch.cuda.synchronize()
+        launches += 1
+        if all(d == t for d, t in (p.progress() for p in plans)):
+            break
+    assert all(d == t for d, t in (p.progress() for p in plans))
+    for j in jobs:
+        assert j.proof_bytes() == j.oracle_bytes(), j.spec
+    for p in plans:
+        p.close()
