@@ -437,9 +437,26 @@ __device__ __forceinline__ void body_p1_init_round(const Step& st, uint32_t tile
 // round's message, so the products by r stay off the chain of hashes.
 __device__ __forceinline__ void finish_reduced_round(const Fr* partials, uint32_t ntiles, DevState* S, Fr* r_out,
                                      uint32_t* msg) {
-  Fr tot[2];
-  sum_partials<2>(partials, ntiles, tot);
   const uint32_t wid = threadIdx.x >> 6;
+  // wave 0 fetches the transcript state while the partials are summed
+  Sha256State st;
+  if (wid == 0) st = load_state(S);
+  Fr tot[2];
+  if (ntiles <= 64) {
+    // every partial fits in wave 0: a wave sum, no LDS round trip
+    tot[0] = fr_zero();
+    tot[1] = fr_zero();
+    if (wid == 0) {
+      if (threadIdx.x < ntiles) {
+        tot[0] = ldf(partials, 2ull * threadIdx.x);
+        tot[1] = ldf(partials, 2ull * threadIdx.x + 1);
+      }
+      tot[0] = lane_fr(wave_sum_to_lane63(tot[0]), 63);
+      tot[1] = lane_fr(wave_sum_to_lane63(tot[1]), 63);
+    }
+  } else {
+    sum_partials<2>(partials, ntiles, tot);
+  }
   bool pend = false;
   Fr claim, pe0, pe2, pr;
   uint32_t* pmsg = nullptr;
@@ -453,9 +470,9 @@ __device__ __forceinline__ void finish_reduced_round(const Fr* partials, uint32_
       pmsg = S->pend_msg;
     }
   }
+  // wave 1 has read the pending round before wave 0 overwrites it
   __syncthreads();
   if (wid == 0) {
-    Sha256State st = load_state(S);
     const Fr r = round_hash_wave(st, tot[0], tot[1]);
     if (threadIdx.x == 0) {
       save_state(S, st);
