@@ -22,15 +22,22 @@ namespace gkr {
 // where this one stopped. ctl[0] = jobs finished in this launch, ctl[2] =
 // steps completed.
 // The launch bound (two workgroups per CU, up to 256 vector registers per
-// lane) keeps every value of this large kernel in registers: builds that
-// spilled vector registers to scratch memory gave wrong proofs in runs that
-// stop and resume, and the build refuses spills.
+// lane) keeps every value of this large kernel in registers; the build
+// refuses kernels that spill, which guards the occupancy target (a spilled
+// build once gave wrong proofs in stop/resume runs, when the end-of-tile
+// release relied on an s_waitcnt builtin; see the release below).
 __global__ void __launch_bounds__(kBlock, 2) k_batch(BatchArgs a) {
   __shared__ uint32_t sh_job, sh_step, sh_tile, sh_state;  // state: 0 work, 1 none, 2 exit
+  __shared__ uint32_t sh_acquire;  // 1: the claimed tile's (job, step) needs an acquire
   __shared__ Step sh_st;
   uint32_t* ctl = a.ctl;
   const uint32_t njobs = a.njobs;
   uint32_t start = (blockIdx.x * 2654435761u) % njobs;
+  // The (job, step) this workgroup last acquired for (thread 0). Further tiles
+  // of the same step need no new acquire: their inputs are outputs of earlier
+  // steps, all published before that acquire, and nothing rewrites a step's
+  // inputs while the step runs, so no stale line can have entered the caches.
+  uint32_t acq_job = ~0u, acq_step = ~0u;
   for (;;) {
     if (threadIdx.x == 0) {
       uint32_t state = 1;
@@ -42,7 +49,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_batch(BatchArgs a) {
           const uint32_t j = (start + scan) % njobs;
           const BatchJobDev& jb = a.jobs[j];
           uint32_t* ctr = jb.ctr;
-          const uint32_t s = __hip_atomic_load(&ctr[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          // relaxed: the acquire fence below runs once a tile is claimed
+          const uint32_t s = __hip_atomic_load(&ctr[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (s >= jb.nsteps) continue;
           unfinished = true;
           const uint32_t nt = jb.steps[s].ntiles;
@@ -52,6 +60,9 @@ __global__ void __launch_bounds__(kBlock, 2) k_batch(BatchArgs a) {
             sh_job = j;
             sh_step = s;
             sh_tile = t;
+            sh_acquire = (j != acq_job || s != acq_step) ? 1u : 0u;
+            acq_job = j;
+            acq_step = s;
             state = 0;
             start = j;  // stay with this job while it has tiles
           }
@@ -76,20 +87,31 @@ __global__ void __launch_bounds__(kBlock, 2) k_batch(BatchArgs a) {
       uint32_t* dst = reinterpret_cast<uint32_t*>(&sh_st);
       for (uint32_t k = threadIdx.x; k < sizeof(Step) / 4; k += kBlock) dst[k] = src[k];
     }
-    // acquire (one wave: the L1 and L2 invalidation covers the whole workgroup
-    // after the barrier): see the writes of the previous steps
-    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // Acquire the writes of the previous steps (published by the release store
+    // of ctr[0] the scan read): one wave invalidates (the CU's L1 and this
+    // XCD's L2 copies of lines other XCDs write) and waits for the
+    // invalidation to complete before the barrier, so no wave of the workgroup
+    // loads before it is done. (Without the wait the barrier does not hold the
+    // other waves back, and their loads could hit stale lines while the
+    // invalidation is in flight.)
+    if (threadIdx.x < 64 && sh_acquire) acquire_agent_wait();
     __syncthreads();
     run_step_tile(sh_st, tile, sh_st.ntiles);
-    // release this tile's writes before it is counted done (workgroups on
-    // other XCDs read these tables in the next step): every wave waits for its
-    // own stores to complete, then one wave writes the L2 back
-    __builtin_amdgcn_s_waitcnt(0);
+    // Release this tile's writes before it is counted done (workgroups on
+    // other XCDs read these tables in the next step): every wave waits until
+    // its stores have reached the L2 (the compiler moves no store below the
+    // wait), then, after the barrier, one wave writes the L2 back and waits for
+    // the write-back before it counts the tile. A workgroup-scope barrier
+    // alone does not wait for global stores on this chip, and an s_waitcnt
+    // builtin is no compiler memory barrier, so neither orders another wave's
+    // stores before the counter update.
+    wait_vmem();
     __syncthreads();
+    if (threadIdx.x < 64) release_agent_wait();
     if (threadIdx.x == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       uint32_t* ctr = jb.ctr;
-      const uint32_t d = atomicAdd(&ctr[1 + jb.nsteps + s], 1u);
+      const uint32_t d = __hip_atomic_fetch_add(&ctr[1 + jb.nsteps + s], 1u, __ATOMIC_RELEASE,
+                                                __HIP_MEMORY_SCOPE_AGENT);
       if (d == sh_st.ntiles - 1) {
         __threadfence();
         const uint32_t done_steps = atomicAdd(&ctl[2], 1u) + 1;

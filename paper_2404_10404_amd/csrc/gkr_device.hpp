@@ -64,6 +64,27 @@ __device__ __forceinline__ Fr wave_sum_to_lane63(Fr v) {
   return v;
 }
 
+// Waits until every vector memory operation this wave has issued is
+// complete (a store has reached the L2; a cache write-back or invalidation
+// has finished). An asm statement with a memory clobber: the compiler moves no
+// memory operation across it and does not drop it, unlike the s_waitcnt
+// builtin, which it treats as touching no memory.
+__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Agent-scope fences that also wait for their cache maintenance: the fence
+// builtin orders the compiler and emits the L2 write-back (release) or the
+// L1/L2 invalidation (acquire); the wait makes it complete before this wave's
+// next instruction, so a workgroup barrier after it orders every wave of the
+// workgroup behind it.
+__device__ __forceinline__ void release_agent_wait() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  wait_vmem();
+}
+__device__ __forceinline__ void acquire_agent_wait() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  wait_vmem();
+}
+
 template <class T>
 __device__ __forceinline__ T P(const Step& st, int i) {
   return reinterpret_cast<T>(const_cast<void*>(st.p[i]));
@@ -146,9 +167,10 @@ __device__ void write_partial(Fr (&v)[NV], Fr* partials, uint32_t tile) {
 // last of ntiles tiles, which then sees all tiles' writes. The counter is back
 // at zero afterwards.
 // Only the partial sums (written by thread 0) cross tiles here, so thread 0
-// counts the tile with a release read-modify-write (an L2 write-back, no
-// invalidation) and only the last tile pays for an acquire (L2 invalidation
-// on this chip's per-XCD caches).
+// counts the tile with a release read-modify-write (an L2 write-back of its
+// own earlier stores, no invalidation) and only the last tile pays for an
+// acquire (L2 invalidation on this chip's per-XCD caches), in every one of
+// its waves (each wave's own loads are ordered after its own invalidation).
 __device__ __forceinline__ bool last_tile(uint32_t* counter, uint32_t ntiles) {
   __shared__ int is_last;
   __syncthreads();
