@@ -15,9 +15,12 @@ device. Two executors:
                   latency-bound rounds overlap another's bandwidth-bound
                   sweeps. Completion is seen by polling an event per job.
   GpuExecutor     the running set is proved by epochs of the persistent
-                  batch kernel; an epoch ends when any job finishes, finished
-                  jobs retire, new ones are admitted, and the next epoch
-                  continues every unfinished job where it stopped.
+                  batch kernel; an epoch ends when any job finishes or, when
+                  a queued request could be admitted at its arrival, after a
+                  step budget sized to end near that arrival (steps are timed
+                  as they run); finished jobs retire, new ones are admitted,
+                  and the next epoch continues every unfinished job where it
+                  stopped.
 
 The plain one-job-at-a-time loop over the same trace is `serve_plain`.
 Latency = completion - arrival; p50/p99 use the nearest-rank definition.
@@ -165,18 +168,41 @@ def serve(requests: Sequence[Request], executor: Executor, max_slots: int, budge
 
 
 class GpuExecutor(Executor):
-    """Runs admitted requests as plans of the persistent batch kernel."""
+    """Runs admitted requests as plans of the persistent batch kernel.
 
-    def __init__(self, epoch_step_budget: int = 0, keep_proofs: bool = True, workgroups: int = -1):
-        import torch
+    epoch_step_budget caps every epoch (0: no cap). When the server passes a
+    timeout (the next arrival could be admitted then), the epoch's step
+    budget is timeout / (seconds per step), the rate measured over earlier
+    epochs (min_steps before the first measurement, and never below it), so
+    the epoch ends near the arrival instead of at the next completion.
+    """
 
-        from . import gkr
-        self.gkr = gkr
-        self.torch = torch
+    def __init__(self, epoch_step_budget: int = 0, keep_proofs: bool = True, workgroups: int = -1,
+                 min_steps: int = 64, gkr_module=None, torch_module=None,
+                 clock: Callable[[], float] = time.perf_counter):
+        if torch_module is None:
+            import torch as torch_module
+        if gkr_module is None:
+            from . import gkr as gkr_module
+        self.gkr = gkr_module
+        self.torch = torch_module
         self.budget = epoch_step_budget
         self.keep = keep_proofs
         self.workgroups = workgroups
-        self.ctl = torch.zeros(4, dtype=torch.int32, device="cuda")
+        self.min_steps = max(1, int(min_steps))
+        self.clock = clock
+        self.sec_per_step = None  # measured: epoch wall time / steps completed
+        self.ctl = self.torch.zeros(4, dtype=self.torch.int32, device="cuda")
+
+    def epoch_budget(self, timeout: Optional[float]) -> int:
+        """Step budget of the next epoch (0 = run until some job finishes)."""
+        if timeout is None:
+            return self.budget
+        if self.sec_per_step is None:
+            b = self.min_steps
+        else:
+            b = max(self.min_steps, int(timeout / self.sec_per_step))
+        return min(b, self.budget) if self.budget else b
 
     def footprint(self, r: Request) -> int:
         c = r.circuit
@@ -195,13 +221,24 @@ class GpuExecutor(Executor):
 
     def epoch(self, running, timeout=None):
         live = [s for s in running if not s["done"]]
+        budget = self.epoch_budget(timeout)
+        t0 = self.clock()
+        steps = finished = 0
         for k in range(0, len(live), 64):
             self.gkr.run_batch([s["plan"] for s in live[k:k + 64]], self.ctl, workgroups=self.workgroups,
-                               step_budget=self.budget, stop_on_finish=True)
-        self.torch.cuda.synchronize()
-        for s in live:
-            d, t = s["plan"].progress()
-            s["done"] = d == t
+                               step_budget=budget, stop_on_finish=True)
+            self.torch.cuda.synchronize()
+            ctl = self.ctl.tolist() if hasattr(self.ctl, "tolist") else list(self.ctl)  # one read
+            finished += int(ctl[0])
+            steps += int(ctl[2])
+        dt = self.clock() - t0
+        if steps > 0:
+            rate = dt / steps
+            self.sec_per_step = rate if self.sec_per_step is None else 0.5 * (self.sec_per_step + rate)
+        if finished:  # ctl[0] counts the plans that finished in the launch
+            for s in live:
+                d, t = s["plan"].progress()
+                s["done"] = d == t
 
     def finished(self, slot) -> bool:
         return slot["done"]

@@ -105,3 +105,110 @@ def test_nearest_rank():
 def test_admission_rejects_bad_config():
     with pytest.raises(ValueError):
         serve.Admission(0, 10)
+
+
+class _FakePlan:
+    def __init__(self, total):
+        self.total, self.done = total, 0
+
+    def progress(self):
+        return self.done, self.total
+
+    def close(self):
+        pass
+
+
+class _FakeDevice:
+    """Stand-in for the binding and torch under GpuExecutor: run_batch advances
+    the plans round-robin one step at a time (each step costs `dt` on the fake
+    clock) until the step budget is spent or, with stop_on_finish, a plan
+    finishes, and reports the steps it ran in ctl[2], as the persistent kernel
+    does."""
+
+    int32 = "int32"
+
+    class cuda:
+        @staticmethod
+        def synchronize():
+            pass
+
+    def __init__(self, clock, steps, dt):
+        self.clock, self.steps, self.dt = clock, steps, dt
+        self.budgets = []
+
+    # torch-like
+    def zeros(self, n, dtype=None, device=None):
+        return [0] * n
+
+    def empty(self, shape, dtype=None, device=None):
+        return None
+
+    # binding-like
+    def device_elements(self, arr):
+        return arr
+
+    def alloc_bytes(self, n):
+        return None
+
+    def make_job(self, c, d_in, seed, out, proof, ws):
+        return seed
+
+    def Plan(self, job):
+        return _FakePlan(self.steps[job])
+
+    def run_batch(self, plans, ctl, workgroups=-1, step_budget=0, stop_on_finish=False):
+        self.budgets.append(step_budget)
+        n = fin = 0
+        stop = False
+        while not stop and any(p.done < p.total for p in plans):
+            for p in plans:
+                if p.done >= p.total:
+                    continue
+                p.done += 1
+                n += 1
+                fin += p.done == p.total
+                self.clock.t += self.dt
+                if (stop_on_finish and p.done == p.total) or (step_budget and n >= step_budget):
+                    stop = True
+                    break
+        ctl[0], ctl[2] = fin, n
+
+
+class _FakeCircuit:
+    depth = 1
+    workspace_bytes = 1000
+    proof_bytes = 100
+
+    def s(self, i):
+        return 4
+
+
+def test_persistent_executor_admits_an_arrival_before_running_jobs_finish():
+    """A request that arrives while a slot is free is admitted near its
+    arrival, not when the long job already on the device finishes: the epoch
+    is cut by a step budget sized from the measured step time."""
+    clock = FakeClock()
+    dev = _FakeDevice(clock, steps={0: 2000, 1: 20}, dt=0.001)
+    ex = serve.GpuExecutor(keep_proofs=False, min_steps=16, gkr_module=dev, torch_module=dev, clock=clock.now)
+    reqs = [serve.Request(rid=i, circuit=_FakeCircuit(), inputs=None, seed=i, arrival=a)
+            for i, a in enumerate([0.0, 0.5])]
+    res = serve.serve(reqs, ex, max_slots=4, budget_bytes=10 ** 9, clock=clock.now, sleep=clock.sleep)
+    assert res[1].admitted < res[0].done, "the arrival waited for the running job to finish"
+    assert res[1].admitted - reqs[1].arrival < 0.05
+    assert res[1].done < res[0].done
+    assert ex.sec_per_step == pytest.approx(0.001)
+    assert all(b > 0 for b in dev.budgets[:2])  # epochs before the arrival had a budget
+
+
+def test_persistent_executor_budget_rule():
+    clock = FakeClock()
+    dev = _FakeDevice(clock, steps={}, dt=0.001)
+    ex = serve.GpuExecutor(epoch_step_budget=0, gkr_module=dev, torch_module=dev, clock=clock.now, min_steps=8)
+    assert ex.epoch_budget(None) == 0          # no arrival pending: run until a job finishes
+    assert ex.epoch_budget(1.0) == 8           # no measurement yet
+    ex.sec_per_step = 0.002
+    assert ex.epoch_budget(1.0) == 500
+    assert ex.epoch_budget(0.0) == 8           # never below min_steps
+    capped = serve.GpuExecutor(epoch_step_budget=100, gkr_module=dev, torch_module=dev, clock=clock.now)
+    capped.sec_per_step = 0.002
+    assert capped.epoch_budget(1.0) == 100 and capped.epoch_budget(None) == 100
