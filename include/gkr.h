@@ -82,15 +82,31 @@ extern "C" {
 #define GKR_MAX_LOG_COPIES 24u
 #define GKR_MAX_DEPTH 4096u
 
+/* An element of the BN254 scalar field Fr, the field the paper proves over
+ * (Section 4.1, choice of the finite field): the canonical value (< p) as
+ * eight little-endian 32-bit limbs. */
 typedef struct {
   uint32_t limb[8];
 } gkr_fr;
 
-/* One gate of a sub-circuit: inputs x, y index the next layer of the same
- * copy; type is GKR_GATE_ADD or GKR_GATE_MUL. */
+/* One gate of a sub-circuit (Section 2.2: a gate of layer i adds or
+ * multiplies two values of layer i+1, which the wiring predicates add_i and
+ * mult_i encode): inputs x, y index the next layer of the same copy; type is
+ * GKR_GATE_ADD or GKR_GATE_MUL. `reserved` is ignored. 12 bytes. */
 typedef struct {
-  uint32_t x, y, type;
+  uint32_t x, y;
+  uint8_t type;
+  uint8_t reserved[3];
 } gkr_gate;
+
+/* The Fiat-Shamir transcript state: the SHA-256 chaining value as 32 bytes
+ * (eight big-endian words). The paper's protocol is interactive (the
+ * verifier sends a random challenge after every round, Section 3.2.1); this
+ * state carries the non-interactive form of those challenges described at the
+ * top of this file. The entry points below take it in device memory. */
+typedef struct {
+  uint8_t state[32];
+} gkr_transcript;
 
 typedef struct gkr_circuit gkr_circuit;
 
@@ -98,10 +114,12 @@ typedef struct gkr_circuit gkr_circuit;
 const char* gkr_last_error(void);
 
 /*
- * Create a circuit: `depth` gate layers (1..GKR_MAX_DEPTH), 2^log_copies
- * copies, log_sub_width[0..depth] = sigma_i (layer 0 = output, [depth] =
- * input), gates[i] = 2^{sigma_i} gates of layer i's sub-circuit (host memory,
- * copied). Validates every index, builds the wiring indexes by x and by y,
+ * Create a circuit (Section 2.2: a layered circuit, layer 0 the output and
+ * layer d the input; Section 3.2: 2^n identical sub-circuits, one per worker
+ * share, here one copy index): `depth` gate layers (1..GKR_MAX_DEPTH),
+ * 2^log_copies copies, log_sub_width[0..depth] = sigma_i (layer 0 = output,
+ * [depth] = input), gates[i] = 2^{sigma_i} gates of layer i's sub-circuit
+ * (host memory, copied). Validates every index, builds the wiring indexes by x and by y,
  * uploads them to the current device and computes the circuit digest. The
  * circuit is immutable and may be used from several streams at once. When no
  * HIP device is present the circuit is created host-only: gkr_verify works
@@ -122,8 +140,10 @@ size_t gkr_layer_proof_bytes(const gkr_circuit* circuit, uint32_t layer);
 uint64_t gkr_gate_layers(const gkr_circuit* circuit);
 
 /*
- * Whole proof (forward evaluation, statement binding, output claim, every
- * layer). d_inputs: 2^{s_d} canonical inputs. Writes d_outputs (2^{s_0}
+ * Whole proof (Section 2.2: the prover evaluates the circuit, then reduces
+ * the claim about the outputs layer by layer to a claim about the inputs;
+ * each layer as in gkr_prove_layer): forward evaluation, statement binding,
+ * output claim, every layer. d_inputs: 2^{s_d} canonical inputs. Writes d_outputs (2^{s_0}
  * elements) and the proof into d_proof (device, proof_cap bytes);
  * *proof_len (host) receives gkr_proof_bytes(). d_ws: gkr_workspace_bytes()
  * bytes of device memory owned by this call until the stream reaches its end;
@@ -137,28 +157,37 @@ int32_t gkr_prove_circuit(const gkr_circuit* circuit, const gkr_fr* d_inputs, ui
                           void* d_ws, size_t ws_bytes, void* stream);
 
 /*
- * Bind the statement: d_state (32 bytes, device) receives the transcript state
- * after init(seed) and the three "GKRD" absorbs. d_inputs / d_outputs are the
+ * Bind the statement (Section 2.2: the prover claims that the outputs are the
+ * circuit evaluated on the inputs; the challenges that follow must depend on
+ * that statement): d_transcript (device) receives the transcript state after
+ * init(seed) and the three "GKRD" absorbs. d_inputs / d_outputs are the
  * canonical input (2^{s_d}) and output (2^{s_0}) vectors.
  */
 int32_t gkr_transcript_init(const gkr_circuit* circuit, uint64_t seed, const gkr_fr* d_inputs,
-                            const gkr_fr* d_outputs, uint8_t* d_state, void* d_ws, size_t ws_bytes,
-                            void* stream);
+                            const gkr_fr* d_outputs, gkr_transcript* d_transcript, void* d_ws,
+                            size_t ws_bytes, void* stream);
 
 /*
- * Output claim: squeezes g (s_0 challenges) from d_state (updated in place)
- * and evaluates the output MLE there. Writes d_g (s_0 elements, variable 1
- * first) and d_claim (1 element) = V_0~(g).
+ * Output claim (Section 2.2: the verifier picks a random point g and the
+ * protocol starts from the claim V_0~(g) about the outputs' multilinear
+ * extension): squeezes g (s_0 challenges) from d_transcript (updated in
+ * place) and evaluates the output MLE there. Writes d_g (s_0 elements,
+ * variable 1 first) and d_claim (1 element) = V_0~(g).
  */
-int32_t gkr_output_claim(const gkr_circuit* circuit, const gkr_fr* d_outputs, uint8_t* d_state,
+int32_t gkr_output_claim(const gkr_circuit* circuit, const gkr_fr* d_outputs, gkr_transcript* d_transcript,
                          gkr_fr* d_g, gkr_fr* d_claim, void* d_ws, size_t ws_bytes, void* stream);
 
 /*
- * One gate layer: reduces claims about V_layer~ to claims about V_{layer+1}~.
+ * One gate layer (Section 2.2: the sumcheck over the layer relation reduces
+ * claims about V_layer~ to claims about V_{layer+1}~ at the points r_x, r_y;
+ * Section 2.3: Libra's linear-time prover runs it in two phases, x then y,
+ * over bookkeeping tables; Section 3.2.1: the copy variables are bound after
+ * the sub-circuit variables): reduces claims about V_layer~ to claims about
+ * V_{layer+1}~.
  *   d_next      V_{layer+1}, 2^{s_{layer+1}} canonical elements
  *   d_u, d_v    points (s_layer elements each); d_v is ignored for layer 0
  *   d_claim_u/v claimed values V_layer~(u), V_layer~(v); d_claim_v ignored for layer 0
- *   d_state     transcript state (32 bytes), read then updated in place. For
+ *   d_transcript transcript state (device), read then updated in place. For
  *               layer 0 it is the state after the output point was squeezed;
  *               for later layers, after the previous layer's last absorb.
  * For layer > 0 the call squeezes alpha, beta and proves alpha*V~(u) + beta*V~(v);
@@ -169,12 +198,14 @@ int32_t gkr_output_claim(const gkr_circuit* circuit, const gkr_fr* d_outputs, ui
  */
 int32_t gkr_prove_layer(const gkr_circuit* circuit, uint32_t layer, const gkr_fr* d_next,
                         const gkr_fr* d_u, const gkr_fr* d_v, const gkr_fr* d_claim_u,
-                        const gkr_fr* d_claim_v, uint8_t* d_state, gkr_fr* d_rx, gkr_fr* d_ry,
+                        const gkr_fr* d_claim_v, gkr_transcript* d_transcript, gkr_fr* d_rx, gkr_fr* d_ry,
                         gkr_fr* d_vx, gkr_fr* d_vy, uint8_t* d_layer_proof, void* d_ws,
                         size_t ws_bytes, void* stream);
 
 /*
- * Batched proving (many proofs at once in one persistent kernel).
+ * Batched proving (many proofs at once in one persistent kernel). The paper
+ * runs one prover per worker; batching many proofs in one launch is this
+ * library's own (no passage defines it).
  *
  * A job names a circuit, its inputs, seed and output/proof/workspace buffers
  * (the buffers gkr_prove_circuit takes). gkr_plan_create records the job's
@@ -224,15 +255,19 @@ int32_t gkr_plan_progress(const gkr_plan* plan, uint32_t* done_steps, uint32_t* 
 int32_t gkr_prove_batch(const gkr_job* jobs, uint32_t n, void* stream);
 
 /*
- * Verifier (host only, synchronous). inputs / outputs / proof are host
- * buffers. Returns 1 (accept), 0 (reject) or a negative status for malformed
+ * Verifier (Section 2.2: the verifier's side of the protocol, ending with
+ * the wiring predicates add~, mult~ at (r_x, r_y) and the inputs' MLE;
+ * Section 3.2.1: every round's polynomial must satisfy g_j(0) + g_j(1) = the
+ * running claim, which then becomes g_j(r_j)). Host only, synchronous.
+ * inputs / outputs / proof are host buffers. Returns 1 (accept), 0 (reject) or a negative status for malformed
  * arguments: GKR_EINVAL for a proof of the wrong length or any element >= p.
  */
 int32_t gkr_verify(const gkr_circuit* circuit, const gkr_fr* inputs, const gkr_fr* outputs,
                    uint64_t seed, const uint8_t* proof, size_t proof_len);
 
 /*
- * Round-schedule tuning (process-wide; used by the autotuner). Proof bytes
+ * Round-schedule tuning (process-wide; used by the autotuner; this library's
+ * own, no passage). Proof bytes
  * never depend on it. tail_log: tables of at most 2^tail_log entries finish
  * their phase in one workgroup (1..20); max_round_blocks: cap on the
  * workgroups of one grid-wide round (1..4096); pairs_per_thread: a grid-wide
@@ -245,7 +280,7 @@ int32_t gkr_set_tuning(uint32_t tail_log, uint32_t max_round_blocks, uint32_t pa
 int32_t gkr_get_tuning(uint32_t* tail_log, uint32_t* max_round_blocks, uint32_t* pairs_per_thread);
 
 /*
- * Kernel timing for measurement. While enabled, every launch is bracketed by
+ * Kernel timing for measurement (this library's own, no passage). While enabled, every launch is bracketed by
  * two HIP events on its own stream (do not enable it while capturing a HIP
  * graph). gkr_profile_read waits for the recorded events and returns, per
  * kernel class, the launch count, the summed event time, and the algorithmic
@@ -262,6 +297,21 @@ typedef struct {
 
 int32_t gkr_profile_enable(int32_t on);
 int32_t gkr_profile_read(gkr_profile_entry* out, uint32_t cap, uint32_t* count);
+
+/*
+ * Integer-multiply microbenchmark of the device's vector ALU (this library's
+ * own, for the roofline of the field-arithmetic kernels; no passage). Runs
+ * one timed launch of `iters` iterations over every compute unit on the
+ * current device and writes the grid-wide rate to *ops_per_s (and the
+ * launch time to *ms, if not null). kind: 0 = v_mad_u64_u32 (32x32+64 ->
+ * 64), 1 = v_mad_u64_u32 with its carry into an overflow word (the
+ * multiply-accumulate of the field product, one operation per pair),
+ * 2 = v_add_u32 (full-rate reference), 3 = v_mul_lo_u32 / v_mul_hi_u32,
+ * 4 = Montgomery field products (the prover's device product). Allocates
+ * and synchronises (not for timed or captured regions). Errors: GKR_EINVAL,
+ * GKR_ENOMEM, GKR_EDEVICE.
+ */
+int32_t gkr_ubench(uint32_t kind, uint32_t iters, double* ops_per_s, double* ms);
 
 #ifdef __cplusplus
 }

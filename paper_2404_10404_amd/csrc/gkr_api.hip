@@ -657,7 +657,7 @@ int32_t gkr_circuit_create(uint32_t depth, uint32_t log_copies, const uint32_t* 
       uint32_t* yent = reinterpret_cast<uint32_t*>(host.data() + offs[5 * i + 4]);
       const std::vector<gkr_gate>& gl = c->gates[i];
       for (size_t z = 0; z < cnt; ++z) {
-        rec[2 * z] = gl[z].x | (gl[z].type << 31);
+        rec[2 * z] = gl[z].x | ((uint32_t)gl[z].type << 31);
         rec[2 * z + 1] = gl[z].y;
         xrow[gl[z].x + 1]++;
         yrow[gl[z].y + 1]++;
@@ -670,9 +670,9 @@ int32_t gkr_circuit_create(uint32_t depth, uint32_t log_copies, const uint32_t* 
       for (size_t z = 0; z < cnt; ++z) {
         const uint32_t kx = fx[gl[z].x]++, ky = fy[gl[z].y]++;
         xent[2 * kx] = (uint32_t)z;
-        xent[2 * kx + 1] = gl[z].y | (gl[z].type << 31);
+        xent[2 * kx + 1] = gl[z].y | ((uint32_t)gl[z].type << 31);
         yent[2 * ky] = (uint32_t)z;
-        yent[2 * ky + 1] = gl[z].x | (gl[z].type << 31);
+        yent[2 * ky + 1] = gl[z].x | ((uint32_t)gl[z].type << 31);
       }
     }
     int ndev = 0;
@@ -747,8 +747,9 @@ uint64_t gkr_gate_layers(const gkr_circuit* c) {
 }
 
 int32_t gkr_transcript_init(const gkr_circuit* c, uint64_t seed, const gkr_fr* d_inputs,
-                            const gkr_fr* d_outputs, uint8_t* d_state, void* d_ws, size_t ws_bytes,
+                            const gkr_fr* d_outputs, gkr_transcript* d_transcript, void* d_ws, size_t ws_bytes,
                             void* stream) {
+  uint8_t* d_state = d_transcript ? d_transcript->state : nullptr;
   if (!c || !d_inputs || !d_outputs || !d_state || !aligned16(d_inputs) || !aligned16(d_outputs)) {
     set_error("null or misaligned argument");
     return GKR_EINVAL;
@@ -770,8 +771,9 @@ int32_t gkr_transcript_init(const gkr_circuit* c, uint64_t seed, const gkr_fr* d
   return check_launch();
 }
 
-int32_t gkr_output_claim(const gkr_circuit* c, const gkr_fr* d_outputs, uint8_t* d_state,
+int32_t gkr_output_claim(const gkr_circuit* c, const gkr_fr* d_outputs, gkr_transcript* d_transcript,
                          gkr_fr* d_g, gkr_fr* d_claim, void* d_ws, size_t ws_bytes, void* stream) {
+  uint8_t* d_state = d_transcript ? d_transcript->state : nullptr;
   if (!c || !d_outputs || !d_state || !d_claim || (!d_g && c->s(0) > 0) || !aligned16(d_outputs) ||
       (d_g && !aligned16(d_g)) || !aligned16(d_claim)) {
     set_error("null or misaligned argument");
@@ -798,7 +800,7 @@ int32_t gkr_output_claim(const gkr_circuit* c, const gkr_fr* d_outputs, uint8_t*
 
 int32_t gkr_prove_layer(const gkr_circuit* c, uint32_t layer, const gkr_fr* d_next,
                         const gkr_fr* d_u, const gkr_fr* d_v, const gkr_fr* d_claim_u,
-                        const gkr_fr* d_claim_v, uint8_t* d_state, gkr_fr* d_rx, gkr_fr* d_ry,
+                        const gkr_fr* d_claim_v, gkr_transcript* d_transcript, gkr_fr* d_rx, gkr_fr* d_ry,
                         gkr_fr* d_vx, gkr_fr* d_vy, uint8_t* d_layer_proof, void* d_ws,
                         size_t ws_bytes, void* stream) {
   if (!c || layer >= c->depth) {
@@ -807,6 +809,7 @@ int32_t gkr_prove_layer(const gkr_circuit* c, uint32_t layer, const gkr_fr* d_ne
   }
   const bool first = layer == 0;
   const uint32_t si = c->s(layer), s1 = c->s(layer + 1);
+  uint8_t* d_state = d_transcript ? d_transcript->state : nullptr;
   if (!d_next || !d_claim_u || !d_state || !d_vx || !d_vy || !d_layer_proof ||
       (si > 0 && !d_u) || (!first && (!d_claim_v || (si > 0 && !d_v))) ||
       (s1 > 0 && (!d_rx || !d_ry))) {

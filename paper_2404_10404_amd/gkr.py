@@ -30,6 +30,7 @@ EXPORTS = (
     "gkr_transcript_init", "gkr_output_claim", "gkr_prove_layer", "gkr_verify",
     "gkr_plan_create", "gkr_plan_destroy", "gkr_plan_reset", "gkr_run_batch", "gkr_plan_progress",
     "gkr_prove_batch", "gkr_set_tuning", "gkr_get_tuning", "gkr_profile_enable", "gkr_profile_read",
+    "gkr_ubench",
 )
 
 
@@ -40,7 +41,11 @@ class GkrError(RuntimeError):
 
 
 class Gate(ctypes.Structure):
-    _fields_ = [("x", ctypes.c_uint32), ("y", ctypes.c_uint32), ("type", ctypes.c_uint32)]
+    """gkr_gate: x, y (u32), type (u8), three reserved bytes. A (count, 3)
+    uint32 array with the type in the third word has this layout (little
+    endian, type < 256)."""
+    _fields_ = [("x", ctypes.c_uint32), ("y", ctypes.c_uint32), ("type", ctypes.c_uint8),
+                ("reserved", ctypes.c_uint8 * 3)]
 
 
 _lib = None
@@ -83,8 +88,10 @@ def lib() -> ctypes.CDLL:
         L.gkr_prove_layer.restype = _i32
         L.gkr_verify.argtypes = [_vp, _vp, _vp, _u64, _vp, _sz]
         L.gkr_verify.restype = _i32
-        L.gkr_set_tuning.argtypes = [_u32, _u32]
+        L.gkr_set_tuning.argtypes = [_u32, _u32, _u32]
         L.gkr_set_tuning.restype = _i32
+        L.gkr_ubench.argtypes = [_u32, _u32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.gkr_ubench.restype = _i32
         _lib = L
         _apply_tuning_cache(L)
     return _lib
@@ -357,6 +364,17 @@ def prove_batch(jobs: Sequence[Job], stream=None):
 
 def set_tuning(tail_log: int, max_round_blocks: int, pairs_per_thread: int = 1):
     _check(_batch_lib().gkr_set_tuning(tail_log, max_round_blocks, pairs_per_thread))
+
+
+UBENCH_KINDS = {0: "v_mad_u64_u32", 1: "v_mad_u64_u32 + v_addc (field multiply-accumulate)",
+                2: "v_add_u32", 3: "v_mul_lo_u32 / v_mul_hi_u32", 4: "Montgomery field product"}
+
+
+def ubench(kind: int, iters: int = 2048) -> Tuple[float, float]:
+    """gkr_ubench: (operations per second over the device, launch ms)."""
+    rate, ms = ctypes.c_double(0), ctypes.c_double(0)
+    _check(lib().gkr_ubench(kind, iters, ctypes.byref(rate), ctypes.byref(ms)))
+    return rate.value, ms.value
 
 
 def get_tuning() -> Tuple[int, int, int]:
