@@ -1,16 +1,26 @@
-"""Benchmark: GKR prover field-gates/s on one MI355X.
+"""Benchmark: GKR prover field-gates/s, batched vs plain, and serving p50/p99
+latency, on one MI355X.
 
 A step is one whole proof (forward evaluation, statement binding, output claim
 and every layer's two sumcheck phases) of the workload over inputs already in
 HBM. `value` = field gates (sum over gate layers of 2^{s_i}) x steps / wall time.
 
-Default workload: 2^8 identical copies of a depth-16 sub-circuit with 2^12
-gates per layer (2^20 gates per layer), half MUL gates, seed 2.
---workload c3: 2^12 copies x 2^14 gates x depth 24 (2^26 gates per layer).
+Default workload (c3): the single-worker share at its real shape, 2^12
+identical copies of a depth-24 sub-circuit with 2^14 gates per layer (2^26
+gates per layer), 30% MUL gates, seed 3. --workload c2: 2^8 copies x depth 16
+x 2^12 gates; c1: one depth-4 circuit of 2^10 gates per layer.
 
-The line also carries the roofline of the dominant kernel class (HIP events
-around each launch during a separate timed pass) and the oracle's rate on a
-bounded slice of the same workload (cpu_baseline).
+The default line also carries:
+  roofline      the dominant kernel class (HIP events around each launch
+                during a separate timed pass on the proof's stream) against
+                the HBM peak or the integer-multiply peak measured live by
+                the library's microbenchmark (gkr_ubench);
+  batched       64 uneven jobs: sequential plain proofs, sequential HIP-graph
+                replays, one persistent launch (proofs vs the oracle's
+                digests);
+  serving       a Poisson trace of the serving mix (256 jobs by default):
+                plain one-at-a-time loop vs continuous batching, p50/p99;
+  cpu_baseline  the oracle on a bounded slice of the same workload.
 """
 import argparse
 import ctypes
@@ -26,10 +36,27 @@ sys.path.insert(0, ROOT)
 import gkr_synth as gs  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# Full-rate 32-bit VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+# Full-rate 32-bit VALU issue (theoretical): 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz. The roofline uses the measured v_mad_u64_u32 rate instead.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# 32x32 multiply-accumulates of one schoolbook Montgomery product with 8 limbs.
+# 32x32 multiply-accumulates of one schoolbook Montgomery product with 8 limbs
+# (64 for the product, 64 + 8 for the reduction).
 MACS_PER_MULMOD = 2 * 8 * 8 + 8
+
+
+def log(msg):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def alu_peaks(gkr):
+    """Integer-multiply peaks measured on this device by gkr_ubench."""
+    out = {}
+    for kind, key in ((0, "mad_u64_u32_per_s"), (1, "mac_pair_per_s"), (2, "add_u32_per_s"),
+                      (3, "mul_u32_per_s"), (4, "field_products_per_s")):
+        rate, ms = gkr.ubench(kind, 1024 if kind < 4 else 64)
+        out[key] = rate
+    return out
 
 WORKLOADS = {
     "c1": (gs.plain_c1, "plain circuit: depth 4, 2^10 gates/layer"),
@@ -102,19 +129,27 @@ def traffic_record(kernel, workload):
     return None
 
 
-def roofline(prof, workload=None):
+def roofline(prof, workload=None, mac_peak_tops=None):
+    """Roofline of the dominant kernel class: t_roof = max(bytes / HBM peak,
+    multiply-adds / integer-multiply peak); the bound is the larger term.
+    The integer peak is the measured v_mad_u64_u32 rate when given."""
     name, e = max(prof.items(), key=lambda kv: kv[1]["ms"])
     sec = e["ms"] / 1e3
     gbs = e["bytes"] / sec / 1e9
     tops = e["mulmods"] * MACS_PER_MULMOD / sec / 1e12
+    alu_peak = mac_peak_tops if mac_peak_tops else VALU_PEAK_TOPS
     t_hbm = e["bytes"] / (HBM_PEAK_GBS * 1e9)
-    t_alu = e["mulmods"] * MACS_PER_MULMOD / (VALU_PEAK_TOPS * 1e12)
+    t_alu = e["mulmods"] * MACS_PER_MULMOD / (alu_peak * 1e12)
     if t_hbm >= t_alu:
         r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": round(gbs / HBM_PEAK_GBS, 4)}
     else:
-        r = {"bound": "alu", "achieved": round(tops, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
-             "frac": round(tops / VALU_PEAK_TOPS, 4)}
+        r = {"bound": "alu", "achieved": round(tops, 3), "peak": round(alu_peak, 3),
+             "unit": "TOP/s (32x32 multiply-adds)", "frac": round(tops / alu_peak, 4),
+             "peak_source": "measured v_mad_u64_u32 rate (gkr_ubench kind 0)" if mac_peak_tops
+             else "theoretical full-rate VALU"}
+    r["alu_frac"] = round(tops / alu_peak, 4)
+    r["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
     r.update({"kernel": name, "launches_per_step": e["launches"],
               "avg_launch_us": round(e["ms"] * 1e3 / max(1, e["launches"]), 2),
               "hbm_gbs": round(gbs, 1), "alu_tops": round(tops, 3),
@@ -126,7 +161,9 @@ def roofline(prof, workload=None):
 
 
 def cpu_baseline(spec, budget_s=20.0):
-    """The oracle (pure Python, one core) on a slice of the workload with fewer copies."""
+    """The oracle (pure Python, one core) on a slice of the workload with fewer
+    copies; its rate carries over to the whole workload (the prover is linear
+    in the gate count), so a full proof's oracle time is extrapolated."""
     from oracle import circuit as oc
     from oracle import prover as op
     n = 0
@@ -147,9 +184,14 @@ def cpu_baseline(spec, budget_s=20.0):
             break
         n += 1
     sl, dt = sample
-    return {"value": round(sl.gate_layers / dt, 1), "unit": "field-gates/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle proof of the same sub-circuit with 2^%d of the 2^%d copies (%d gate-layers) in %.1f s"
-                      % (sl.log_copies, spec.log_copies, sl.gate_layers, dt)}
+    rate = sl.gate_layers / dt
+    out = {"value": round(rate, 1), "unit": "field-gates/s", "cores": 1, "kind": "oracle",
+           "sample": "oracle proof of the same sub-circuit with 2^%d of the 2^%d copies (%d gate-layers) in %.1f s"
+                     % (sl.log_copies, spec.log_copies, sl.gate_layers, dt)}
+    if sl.log_copies < spec.log_copies:
+        out["extrapolated_full_proof_s"] = round(spec.gate_layers / rate, 1)
+        out["extrapolated"] = True
+    return out
 
 
 def batched_comparison(gkr, steps, warmup):
@@ -180,7 +222,9 @@ def batched_comparison(gkr, steps, warmup):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
+    log("batched: plain sequential proofs")
     t_plain = timed(plain)
+    log("batched: graph capture and replays")
     # the same sequential proofs captured once per job in HIP graphs, then replayed
     graphs = []
     stream = torch.cuda.Stream()
@@ -205,6 +249,7 @@ def batched_comparison(gkr, steps, warmup):
             p.reset()
         gkr.run_batch(plans, ctl)
 
+    log("batched: one persistent launch")
     t_batch = timed(batched)
     # the batched proofs are checked against the oracle digests when available
     exact = None
@@ -237,6 +282,7 @@ def serving_comparison(gkr, njobs, max_slots, budget_gib, util=0.8):
         reqs.append(serve.Request(rid=k, circuit=c, inputs=gs.make_inputs(spec), seed=spec.seed, arrival=0.0,
                                   gate_layers=spec.gate_layers))
     # mean plain service time of the mix (all jobs back to back, after one warm-up job)
+    log("serving: %d requests built; mean plain service time" % len(reqs))
     serve.serve_plain(reqs[:1], keep_proofs=False)
     t0 = time.perf_counter()
     serve.serve_plain(reqs, keep_proofs=False)
@@ -247,10 +293,13 @@ def serving_comparison(gkr, njobs, max_slots, budget_gib, util=0.8):
     for r, g in zip(reqs, gaps):
         t += float(g)
         r.arrival = t
+    log("serving: plain loop on the trace (%.3f arrivals/s)" % rate)
     plain = serve.serve_plain(reqs, keep_proofs=True)
     budget = int(budget_gib * (1 << 30))
+    log("serving: continuous batching, stream executor")
     mixed = serve.serve(reqs, serve.StreamExecutor(keep_proofs=True), max_slots=max_slots, budget_bytes=budget)
     torch.cuda.synchronize()
+    log("serving: continuous batching, persistent-kernel executor")
     persistent = serve.serve(reqs, serve.GpuExecutor(keep_proofs=True), max_slots=max_slots, budget_bytes=budget)
     torch.cuda.synchronize()
     same = all(mixed[r.rid].proof == plain[r.rid].proof == persistent[r.rid].proof and mixed[r.rid].proof is not None
@@ -262,33 +311,54 @@ def serving_comparison(gkr, njobs, max_slots, budget_gib, util=0.8):
         "plain_loop": serve.summary(plain, reqs),
         "continuous_batching": dict(serve.summary(mixed, reqs), executor="4 HIP streams, whole proofs enqueued"),
         "continuous_batching_persistent": dict(serve.summary(persistent, reqs),
-                                               executor="persistent batch kernel, epochs end when a job finishes"),
+                                               executor="persistent batch kernel; an epoch ends when a job "
+                                                        "finishes or near the next admissible arrival"),
         "proofs_identical_alone_and_in_mix": same,
     }
 
 
-def golden_digest(workload):
-    p = os.path.join(ROOT, "tests", "golden", "%s_proof.json" % workload)
+def golden_digest(name):
+    p = os.path.join(ROOT, "tests", "golden", "%s_proof.json" % name)
     if not os.path.exists(p):
         return None
     with open(p) as f:
         return json.load(f).get("proof_sha256")
 
 
+def slice_bit_exact(gkr, spec, log_copies, golden_name):
+    """Prove the same sub-circuit with fewer copies on the GPU and compare the
+    proof digest with the oracle's stored one (None if no golden exists)."""
+    import torch
+    gd = golden_digest(golden_name)
+    if gd is None:
+        return None
+    sl = gs.copy_slice(spec, log_copies)
+    c = gkr.Circuit.from_synth(sl, gs.make_wiring(sl))
+    pr = gkr.Prover(c)
+    pr.prove(gkr.device_elements(gs.make_inputs(sl)), sl.seed)
+    torch.cuda.synchronize()
+    ok = hashlib.sha256(pr.proof_bytes()).hexdigest() == gd
+    del pr, c
+    return ok
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serving", "copy"])
+    ap.add_argument("--no-batched", action="store_true", help="leave out the 64-job batched leg")
+    ap.add_argument("--no-serving", action="store_true", help="leave out the serving leg")
+    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serving", "copy", "ubench"])
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--jobs", type=int, default=256)
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--budget-gib", type=float, default=96.0)
+    ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the prover proves one worker's share on a single MI355X "
@@ -314,6 +384,14 @@ def main():
         print(json.dumps({"mode": "copy", "bytes_per_copy": n, "copies": args.steps,
                           "GB_per_s": round(2 * n * args.steps / dt / 1e9, 1)}), flush=True)
         return
+    if args.mode == "ubench":
+        peaks = alu_peaks(gkr)
+        out = {"mode": "ubench", "theoretical_full_rate_valu_per_s": VALU_PEAK_TOPS * 1e12}
+        out.update({k: round(v, 1) for k, v in peaks.items()})
+        out["mad_vs_full_rate"] = round(peaks["mad_u64_u32_per_s"] / (VALU_PEAK_TOPS * 1e12), 4)
+        out["field_product_macs_per_s"] = round(peaks["field_products_per_s"] * MACS_PER_MULMOD, 1)
+        print(json.dumps(out), flush=True)
+        return
     if args.mode == "serving":
         res = serving_comparison(gkr, args.jobs, args.slots, args.budget_gib)
         cb = res["continuous_batching"]
@@ -335,16 +413,23 @@ def main():
         print(json.dumps(line), flush=True)
         return
 
+    peaks = None
+    if not args.no_profile:
+        log("integer-multiply peaks (gkr_ubench)")
+        peaks = alu_peaks(gkr)
     spec = WORKLOADS[args.workload][0]()
+    log("%s: wiring and inputs" % args.workload)
     wiring = gs.make_wiring(spec)
     inputs = gs.make_inputs(spec)
     c = gkr.Circuit.from_synth(spec, wiring)
     prover = gkr.Prover(c)
     d_in = gkr.device_elements(inputs)
     del inputs
+    log("%s: %d warm-up proofs" % (args.workload, args.warmup))
     for _ in range(args.warmup):
         prover.prove(d_in, spec.seed)
     torch.cuda.synchronize()
+    log("%s: %d timed proofs" % (args.workload, args.steps))
     t0 = time.perf_counter()
     for _ in range(args.steps):
         prover.prove(d_in, spec.seed)
@@ -352,11 +437,13 @@ def main():
     dt = time.perf_counter() - t0
     value = c.gate_layers * args.steps / dt
     proof = prover.proof_bytes()
+    exact = {}
     gd = golden_digest(args.workload)
-    exact = None if gd is None else (hashlib.sha256(proof).hexdigest() == gd)
+    if gd is not None:
+        exact["proof_vs_oracle_golden"] = hashlib.sha256(proof).hexdigest() == gd
 
     line = {
-        "metric": "GKR prover field-gates/sec (plain proof, bit-exact)",
+        "metric": "GKR prover field-gates/sec + p99 job latency, batched vs plain, bit-exact",
         "value": round(value, 1),
         "unit": "field-gates/s",
         "n_gpus": 1,
@@ -370,14 +457,33 @@ def main():
         "data": "synthetic (seeded circuits and inputs; the paper's Ethereum circuits are not available)",
         "config": {"workload": WORKLOADS[args.workload][1], "gate_layers_per_proof": c.gate_layers,
                    "proof_bytes": c.proof_bytes, "seed": spec.seed},
-        "bit_exact_vs_oracle_golden": exact,
     }
     if not args.no_profile:
+        log("%s: profile pass (HIP events per launch)" % args.workload)
         prof = profile_pass(gkr, prover, d_in, spec.seed, args.profile_steps)
-        line["roofline"] = roofline(prof, args.workload)
+        line["roofline"] = roofline(prof, args.workload, peaks["mad_u64_u32_per_s"] / 1e12)
         line["kernels"] = {k: {"ms": round(v["ms"], 4), "launches": v["launches"]} for k, v in
                            sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
+        line["alu_peaks_measured"] = {k: round(v, 1) for k, v in peaks.items()}
+    del prover, d_in
+    torch.cuda.empty_cache()
+    if args.workload == "c3":
+        log("c3: the same sub-circuit with 2^4 copies against the oracle's proof")
+        exact["c3_slice_2^4_copies_vs_oracle_golden"] = slice_bit_exact(gkr, spec, 4, "c3slice")
+        torch.cuda.empty_cache()
+    if not args.no_batched:
+        log("batched leg: 64 uneven jobs")
+        line["batched"] = batched_comparison(gkr, args.batch_steps, 1)
+        exact["batched_64_jobs_vs_oracle_golden"] = line["batched"]["bit_exact_vs_oracle_golden"]
+        torch.cuda.empty_cache()
+    if not args.no_serving:
+        log("serving leg: %d jobs" % args.jobs)
+        line["serving"] = serving_comparison(gkr, args.jobs, args.slots, args.budget_gib)
+        exact["serving_alone_vs_in_mix"] = line["serving"]["proofs_identical_alone_and_in_mix"]
+        torch.cuda.empty_cache()
+    line["bit_exact"] = exact
     if not args.no_cpu_baseline:
+        log("cpu baseline: the oracle on a slice")
         line["cpu_baseline"] = cpu_baseline(spec)
     print(json.dumps(line), flush=True)
 

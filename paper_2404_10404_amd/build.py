@@ -13,7 +13,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgkr.so")
-SOURCES = ["gkr_batch_kernel.hip", "gkr_kernels.hip", "gkr_api.hip", "gkr_tuning.cpp", "gkr_verify.cpp", "gkr_profile.cpp", "gkr_batch.hip"]
+SOURCES = ["gkr_batch_kernel.hip", "gkr_kernels.hip", "gkr_api.hip", "gkr_tuning.cpp", "gkr_verify.cpp",
+           "gkr_profile.cpp", "gkr_batch.hip", "gkr_ubench.hip"]
+# Test helper: the device field-code checker the GPU tests load.
+ROOT = os.path.dirname(HERE)
+CHECKER_SRC = os.path.join(ROOT, "tests", "native", "fr_device_check.hip")
+CHECKER_LIB = os.path.join(ROOT, "tests", "native", "libfrcheck.so")
 ARCH = "gfx950"
 
 # Packed fp32 instructions are switched off for every device compilation.
@@ -60,11 +65,25 @@ def _compile(src: str) -> str:
     return obj
 
 
+def build_checker() -> str:
+    """The device field-code checker of the tests (tests/native/libfrcheck.so)."""
+    tmp = CHECKER_LIB + ".tmp"
+    cmd = [_hipcc(), "-x", "hip", *COMMON, "-shared", "-o", tmp, CHECKER_SRC]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("checker build failed: %s\n%s" % (" ".join(cmd), res.stderr[-4000:]))
+    os.replace(tmp, CHECKER_LIB)
+    return CHECKER_LIB
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(9, len(srcs) + 1)) as ex:
+        checker = ex.submit(build_checker) if os.path.exists(CHECKER_SRC) else None
         objs = list(ex.map(_compile, srcs))
+        if checker is not None:
+            checker.result()
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     res = subprocess.run(cmd, capture_output=True, text=True)
