@@ -157,6 +157,25 @@ int32_t gkr_prove_circuit(const gkr_circuit* circuit, const gkr_fr* d_inputs, ui
                           void* d_ws, size_t ws_bytes, void* stream);
 
 /*
+ * gkr_prove_circuit without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation). The workspace is a static device array
+ * of GKR_NOALLOC_WORKSPACE_BYTES (256 MiB) that every GPU the library runs on
+ * holds until the process ends; the call itself allocates nothing, and the
+ * caller still passes inputs, outputs and the proof buffer as for
+ * gkr_prove_circuit (same bytes, same errors). Circuits whose
+ * gkr_workspace_bytes() exceeds GKR_NOALLOC_WORKSPACE_BYTES are rejected with
+ * GKR_EUNSUPPORTED; the current device must be the circuit's (GKR_EINVAL).
+ * Every call on one GPU shares that GPU's array: calls whose device work
+ * overlaps (streams with no ordering between them) race; calls on one stream
+ * are ordered. The array needs no clearing between calls.
+ */
+#define GKR_NOALLOC_WORKSPACE_BYTES (256ull << 20)
+int32_t gkr_prove_circuit_noalloc(const gkr_circuit* circuit, const gkr_fr* d_inputs, uint64_t seed,
+                                  gkr_fr* d_outputs, uint8_t* d_proof, size_t proof_cap, size_t* proof_len,
+                                  void* stream);
+
+/*
  * Bind the statement (Section 2.2: the prover claims that the outputs are the
  * circuit evaluated on the inputs; the challenges that follow must depend on
  * that statement): d_transcript (device) receives the transcript state after

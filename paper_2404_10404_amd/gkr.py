@@ -30,8 +30,11 @@ EXPORTS = (
     "gkr_transcript_init", "gkr_output_claim", "gkr_prove_layer", "gkr_verify",
     "gkr_plan_create", "gkr_plan_destroy", "gkr_plan_reset", "gkr_run_batch", "gkr_plan_progress",
     "gkr_prove_batch", "gkr_set_tuning", "gkr_get_tuning", "gkr_profile_enable", "gkr_profile_read",
-    "gkr_ubench",
+    "gkr_ubench", "gkr_prove_circuit_noalloc",
 )
+
+# Size of the static workspace of gkr_prove_circuit_noalloc (GKR_NOALLOC_WORKSPACE_BYTES).
+NOALLOC_WORKSPACE_BYTES = 256 << 20
 
 
 class GkrError(RuntimeError):
@@ -90,6 +93,8 @@ def lib() -> ctypes.CDLL:
         L.gkr_verify.restype = _i32
         L.gkr_set_tuning.argtypes = [_u32, _u32, _u32]
         L.gkr_set_tuning.restype = _i32
+        L.gkr_prove_circuit_noalloc.argtypes = [_vp, _vp, _u64, _vp, _vp, _sz, ctypes.POINTER(_sz), _vp]
+        L.gkr_prove_circuit_noalloc.restype = _i32
         L.gkr_ubench.argtypes = [_u32, _u32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.gkr_ubench.restype = _i32
         _lib = L
@@ -232,6 +237,16 @@ def prove_circuit(c: Circuit, d_inputs, seed: int, d_outputs, d_proof, d_ws, str
     _check(lib().gkr_prove_circuit(c.handle, _ptr(d_inputs), seed & (2**64 - 1), _ptr(d_outputs), _ptr(d_proof),
                                    d_proof.numel() * d_proof.element_size(), ctypes.byref(plen), _ptr(d_ws),
                                    d_ws.numel() * d_ws.element_size(), _stream(stream)))
+    return plen.value
+
+
+def prove_circuit_noalloc(c: Circuit, d_inputs, seed: int, d_outputs, d_proof, stream=None) -> int:
+    """gkr_prove_circuit_noalloc (workspace in the library's static device
+    array); returns the proof length."""
+    plen = _sz(0)
+    _check(lib().gkr_prove_circuit_noalloc(c.handle, _ptr(d_inputs), seed & (2**64 - 1), _ptr(d_outputs),
+                                           _ptr(d_proof), d_proof.numel() * d_proof.element_size(),
+                                           ctypes.byref(plen), _stream(stream)))
     return plen.value
 
 
