@@ -45,6 +45,11 @@ PURPOSE_GATE_TYPE = 3
 PURPOSE_INPUT = 4
 PURPOSE_JOB = 5
 PURPOSE_ARRIVAL = 6
+PURPOSE_NEST_COUNT = 7
+PURPOSE_NEST_X = 8
+PURPOSE_NEST_SRC = 9
+PURPOSE_NEST_Y = 10
+PURPOSE_NEST_TYPE = 11
 
 
 def mix64(z: int) -> int:
@@ -280,3 +285,116 @@ def poisson_gaps(count: int, rate: float, trace_seed: int = 2000) -> np.ndarray:
     w = stream(stream_key(trace_seed, PURPOSE_ARRIVAL, 0), count)
     u = (w >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))  # [0, 1)
     return -np.log1p(-u) / rate
+
+
+# ---------------------------------------------------------------- general circuits
+
+@dataclasses.dataclass(frozen=True)
+class GeneralSpec:
+    """Shape of a general (non-layered) data-parallel circuit with accumulation gates.
+
+    Gate z of gate layer i holds 1..max_fanin nested fan-in-2 gates (uniform);
+    each reads its left input x from layer i+1 and its right input y from layer
+    i+1 or, with probability `cross`, from one of the layers i+2 .. i+reach
+    (uniform; capped at the input layer); MUL with probability mu.
+
+    depth, log_copies, log_sub_width, mu, seed  as in CircuitSpec
+    max_fanin   nested gates per gate: uniform in [1, max_fanin]
+    reach       right inputs come from layers i+1 .. min(depth, i + reach)
+    cross       probability (numerator, denominator) of a right input beyond layer i+1
+    """
+
+    depth: int
+    log_copies: int
+    log_sub_width: Tuple[int, ...]
+    max_fanin: int = 2
+    reach: int = 3
+    cross: Tuple[int, int] = (1, 4)
+    mu: Tuple[int, int] = (1, 2)
+    seed: int = 1
+
+    def __post_init__(self):
+        if len(self.log_sub_width) != self.depth + 1:
+            raise ValueError("log_sub_width needs depth + 1 entries")
+        if self.max_fanin < 1 or self.reach < 1:
+            raise ValueError("max_fanin and reach must be at least 1")
+
+    def log_width(self, i: int) -> int:
+        return self.log_sub_width[i] + self.log_copies
+
+    @property
+    def gate_layers(self) -> int:
+        """Sum over gate layers of 2^{s_i} (gates, not nested gates)."""
+        return sum(1 << self.log_width(i) for i in range(self.depth))
+
+
+@dataclasses.dataclass
+class NestedWiring:
+    """The nested gates of one gate layer's sub-circuit, grouped by output gate z
+    (ascending): output z, left input x (layer i+1), right-input layer src, right
+    input y (layer src), type."""
+
+    z: np.ndarray    # uint32
+    x: np.ndarray    # uint32
+    src: np.ndarray  # uint32
+    y: np.ndarray    # uint32
+    kind: np.ndarray  # uint32, GATE_ADD or GATE_MUL
+
+
+def make_general_wiring(spec: GeneralSpec) -> List[NestedWiring]:
+    """Seeded nested-gate lists of every gate layer (see GeneralSpec)."""
+    num, den = spec.mu
+    mul_threshold = (num << 64) // den
+    cnum, cden = spec.cross
+    cross_threshold = (cnum << 32) // cden
+    d = spec.depth
+    out = []
+    for i in range(d):
+        width = 1 << spec.log_sub_width[i]
+        cnt = (stream(stream_key(spec.seed, PURPOSE_NEST_COUNT, i), width) % np.uint64(spec.max_fanin)
+               + np.uint64(1)).astype(np.int64)
+        total = int(cnt.sum())
+        z = np.repeat(np.arange(width, dtype=np.uint32), cnt)
+        x = (stream(stream_key(spec.seed, PURPOSE_NEST_X, i), total)
+             & np.uint64((1 << spec.log_sub_width[i + 1]) - 1)).astype(np.uint32)
+        hi = min(d, i + spec.reach)
+        w = stream(stream_key(spec.seed, PURPOSE_NEST_SRC, i), total)
+        src = np.full(total, i + 1, dtype=np.uint32)
+        if hi > i + 1:
+            far = (w >> np.uint64(32)) < np.uint64(cross_threshold)
+            pick = (i + 2 + (w & np.uint64(0xFFFFFFFF)) % np.uint64(hi - i - 1)).astype(np.uint32)
+            src = np.where(far, pick, src).astype(np.uint32)
+        ymask = np.array([(1 << spec.log_sub_width[j]) - 1 if j <= d else 0 for j in range(d + 1)],
+                         dtype=np.uint64)
+        y = (stream(stream_key(spec.seed, PURPOSE_NEST_Y, i), total) & ymask[src]).astype(np.uint32)
+        t = stream(stream_key(spec.seed, PURPOSE_NEST_TYPE, i), total)
+        if mul_threshold >= 1 << 64:
+            kind = np.full(total, GATE_MUL, dtype=np.uint32)
+        else:
+            kind = np.where(t < np.uint64(mul_threshold), GATE_MUL, GATE_ADD).astype(np.uint32)
+        out.append(NestedWiring(z, x, src, y, kind))
+    return out
+
+
+def make_general_inputs(spec: GeneralSpec, start: int = 0, count: Optional[int] = None) -> np.ndarray:
+    """Input layer V_d of a general circuit (same element stream as make_inputs)."""
+    total = 1 << spec.log_width(spec.depth)
+    if count is None:
+        count = total - start
+    if start < 0 or start + count > total:
+        raise ValueError("input slice out of range")
+    return field_elements(stream_key(spec.seed, PURPOSE_INPUT, 0), count, start)
+
+
+def general_small() -> GeneralSpec:
+    """A small general circuit for parity: 2^4 copies x depth 6, 2^8 gates per layer,
+    up to 4 nested gates per gate, right inputs up to 3 layers back."""
+    return GeneralSpec(depth=6, log_copies=4, log_sub_width=(8,) * 7, max_fanin=4, reach=3, cross=(1, 3),
+                       mu=(1, 2), seed=40)
+
+
+def general_data_parallel() -> GeneralSpec:
+    """General-circuit workload: 2^8 copies x depth 8, 2^12 gates per layer, up to 4 nested
+    gates per gate (accumulation gates), a quarter of the right inputs from 2..4 layers back."""
+    return GeneralSpec(depth=8, log_copies=8, log_sub_width=(12,) * 9, max_fanin=4, reach=4, cross=(1, 4),
+                       mu=(1, 2), seed=41)

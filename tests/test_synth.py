@@ -1,4 +1,6 @@
 """The seeded generator: splitmix64 reference values, canonical uniform elements, shapes."""
+import dataclasses
+
 import numpy as np
 
 import gkr_synth as gs
@@ -65,3 +67,22 @@ def test_threaded_generation_matches_blocks():
     for off in (0, (1 << 20) - 5, (1 << 21) + 100):
         cnt = min(4096, n - off)
         assert np.array_equal(full[off:off + cnt], gs._field_elements_block(key, cnt, off))
+
+
+def test_general_wiring_is_seeded_and_in_range():
+    spec = gs.GeneralSpec(depth=5, log_copies=2, log_sub_width=(3, 4, 2, 5, 3, 4), max_fanin=3, reach=3,
+                          cross=(1, 2), seed=9)
+    a, b = gs.make_general_wiring(spec), gs.make_general_wiring(spec)
+    for i, (w, v) in enumerate(zip(a, b)):
+        for f in ("z", "x", "src", "y", "kind"):
+            assert (getattr(w, f) == getattr(v, f)).all()
+        assert (w.z[1:] >= w.z[:-1]).all()  # grouped by output gate
+        counts = np.bincount(w.z, minlength=1 << spec.log_sub_width[i])
+        assert counts.min() >= 1 and counts.max() <= spec.max_fanin
+        assert (w.x < 1 << spec.log_sub_width[i + 1]).all()
+        assert ((w.src > i) & (w.src <= min(spec.depth, i + spec.reach))).all()
+        for j in np.unique(w.src):
+            assert (w.y[w.src == j] < 1 << spec.log_sub_width[j]).all()
+    other = gs.make_general_wiring(dataclasses.replace(spec, seed=10))
+    assert any((w.x != v.x).any() for w, v in zip(a, other) if len(w.x) == len(v.x)) or \
+        [len(w.x) for w in a] != [len(w.x) for w in other]
