@@ -108,6 +108,20 @@ typedef struct {
   uint8_t state[32];
 } gkr_transcript;
 
+/* One nested gate of a general circuit (Section 2.7, general arithmetic
+ * circuit: a gate may read any later layer as long as one input is in the
+ * next layer; Section 3.4.3, accumulation gate: a gate holds a list of nested
+ * fan-in-2 gates, possibly of different types and reading different layers,
+ * and its value is their sum). In gate layer i: output gate z, left input x
+ * in layer i+1, right input y in layer src (i < src <= depth); type
+ * GKR_GATE_ADD or GKR_GATE_MUL; `reserved` is ignored. 20 bytes. Copies as
+ * for gkr_gate: gate z of copy c reads x*2^n + c and y*2^n + c. */
+typedef struct {
+  uint32_t z, x, src, y;
+  uint8_t type;
+  uint8_t reserved[3];
+} gkr_nested_gate;
+
 typedef struct gkr_circuit gkr_circuit;
 
 /* Message describing the last failure on the calling thread ("" if none). */
@@ -130,6 +144,32 @@ const char* gkr_last_error(void);
 int32_t gkr_circuit_create(uint32_t depth, uint32_t log_copies, const uint32_t* log_sub_width,
                            const gkr_gate* const* gates, gkr_circuit** out);
 void gkr_circuit_destroy(gkr_circuit* circuit);
+
+/*
+ * Create a general circuit (Sections 2.7 and 3.4.3, see gkr_nested_gate):
+ * `depth` gate layers, 2^log_copies copies, log_sub_width[0..depth] = sigma_i,
+ * counts[i] >= 1 nested gates of gate layer i at gates[i] (host memory,
+ * copied; any order). Gate z of layer i is the sum of its nested gates (0 if
+ * it has none). For a pair of layers only the gates the reading layer uses
+ * are indexed: layer i's right inputs are proved over the concatenation of
+ * the used gates of each source layer (increasing source layer, each block
+ * 2^tau_i entries, zero padded), and the prover then sends every block's
+ * value at the local part of the phase-2 point; those values are claims on
+ * the source layers, combined at the start of each layer with squeezed
+ * coefficients. Proof of layer i: s_{i+1} phase-1 messages, vx, rho_i
+ * phase-2 messages (rho_i = block bits + tau_i + n), vy, then one value per
+ * source layer; the circuit digest is SHA256("GKR-GENERAL-v1" || LE32 depth,
+ * log_copies, sigma_0..sigma_depth || per gate layer LE32 count || per nested
+ * gate LE32 z, x, src, y || u8 type). gkr_prove_circuit, the no-allocation
+ * variant, gkr_transcript_init, gkr_output_claim and gkr_verify accept the
+ * result; gkr_prove_layer and the batch calls return GKR_EUNSUPPORTED for it.
+ * A gate layer may be read by at most 13 earlier layers. Errors: GKR_EINVAL
+ * (bad shape or nested gate), GKR_EUNSUPPORTED (too large), GKR_ENOMEM,
+ * GKR_EDEVICE.
+ */
+int32_t gkr_general_circuit_create(uint32_t depth, uint32_t log_copies, const uint32_t* log_sub_width,
+                                   const uint64_t* counts, const gkr_nested_gate* const* gates,
+                                   gkr_circuit** out);
 
 /* Device workspace one proof needs (layer store + bookkeeping tables + state). */
 size_t gkr_workspace_bytes(const gkr_circuit* circuit);

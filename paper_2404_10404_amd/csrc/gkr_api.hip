@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "gkr_general.hpp"
 #include "gkr_kernels.hpp"
 #include "gkr_program.hpp"
 #include "gkr_tuning.hpp"
@@ -401,7 +402,10 @@ void Program::state_import(DevState* S, const uint8_t* in) {
 }
 
 void Program::run(hipStream_t s) const {
-  for (const Step& st : steps) launch_step(st, s);
+  for (const Step& st : steps) {
+    if (st.type >= ST_G_GATHER) launch_general_step(st, s);
+    else launch_step(st, s);
+  }
 }
 
 // ------------------------------------------------------------------ proof programs
@@ -430,6 +434,11 @@ static void emit_phase(Program& pg, const Fr* const* src0, Fr* const* dst, uint3
   }
   const uint64_t size = pending ? 2 * eval : eval;
   pg.tail<NT>(src, dst, size, pending, nrounds - j, S, r_out + j, msg + 24 * j, final_out, proof_value);
+}
+
+void emit_phase_a(Program& pg, const Fr* const* src0, Fr* const* dst, uint32_t nrounds, DevState* S, Fr* partials,
+                  Fr* r_out, uint32_t* msg, Fr* final_out, uint32_t* proof_value, const Tuning& tun) {
+  emit_phase<3>(pg, src0, dst, nrounds, S, partials, r_out, msg, final_out, proof_value, tun);
 }
 
 // One gate layer (A3-A7). W = V_{i+1} in Montgomery form; u, v points of
@@ -506,7 +515,18 @@ static void emit_output_claim(Program& pg, const gkr_circuit& c, const Workspace
   pg.wsum(w.layer[0], w.aU, w.Cu, c.n, 1ull << c.s(0), w.partials, S, &S->scratch[0], tun);
 }
 
-static size_t layer_proof_words(const gkr_circuit& c, uint32_t i) { return (6ull * c.s(i + 1) + 2) * 8; }
+static size_t layer_proof_words(const gkr_circuit& c, uint32_t i) {
+  if (c.general) return general_layer_proof_bytes(c, i) / 4;
+  return (6ull * c.s(i + 1) + 2) * 8;
+}
+
+void emit_statement_and_output_claim(Program& pg, const gkr_circuit& c, const Workspace& w, const gkr_fr* d_inputs,
+                                     const gkr_fr* d_outputs, uint64_t seed, const Tuning& tun) {
+  pg.digest(d_inputs, 1ull << c.s(c.depth), w.dig_in, w);
+  pg.digest(d_outputs, 1ull << c.s(0), w.dig_out, w);
+  pg.transcript_begin(w.state, seed_state(seed), c.digest, w.dig_in, w.dig_out);
+  emit_output_claim(pg, c, w, tun);
+}
 
 // The whole proof of gkr_prove_circuit as a step program.
 void emit_prove_circuit(Program& pg, const gkr_circuit& c, const Workspace& w, const gkr_fr* d_inputs,
@@ -559,6 +579,11 @@ int32_t check_ws(const gkr_circuit* c, const void* ws, size_t ws_bytes) {
 
 }  // namespace gkr
 
+gkr_circuit::~gkr_circuit() {
+  if (dev_block) hipFree(dev_block);
+  gkr::general_destroy(general);
+}
+
 using namespace gkr;
 
 // ====================================================================== C ABI
@@ -594,6 +619,7 @@ int32_t gkr_circuit_create(uint32_t depth, uint32_t log_copies, const uint32_t* 
     c->n = log_copies;
     c->sigma.assign(log_sub_width, log_sub_width + depth + 1);
     c->gates.resize(depth);
+    // (on the failure paths below `delete c` also frees the device block)
     for (uint32_t i = 0; i < depth; ++i) {
       if (!gates[i]) {
         delete c;
@@ -687,13 +713,13 @@ int32_t gkr_circuit_create(uint32_t depth, uint32_t log_copies, const uint32_t* 
     hipGetDevice(&c->device);
     if (hipMalloc(&c->dev_block, total) != hipSuccess) {
       (void)hipGetLastError();
+      c->dev_block = nullptr;
       delete c;
       set_error("device allocation of the wiring failed");
       return GKR_ENOMEM;
     }
     if (hipMemcpy(c->dev_block, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
       (void)hipGetLastError();
-      hipFree(c->dev_block);
       delete c;
       set_error("upload of the wiring failed");
       return GKR_EDEVICE;
@@ -719,11 +745,7 @@ int32_t gkr_circuit_create(uint32_t depth, uint32_t log_copies, const uint32_t* 
   }
 }
 
-void gkr_circuit_destroy(gkr_circuit* c) {
-  if (!c) return;
-  if (c->dev_block) hipFree(c->dev_block);
-  delete c;
-}
+void gkr_circuit_destroy(gkr_circuit* c) { delete c; }
 
 size_t gkr_workspace_bytes(const gkr_circuit* c) { return c ? c->plan.total : 0; }
 
@@ -734,6 +756,7 @@ size_t gkr_layer_proof_bytes(const gkr_circuit* c, uint32_t layer) {
 
 size_t gkr_proof_bytes(const gkr_circuit* c) {
   if (!c) return 0;
+  if (c->general) return general_proof_bytes(*c);
   size_t t = 0;
   for (uint32_t i = 0; i < c->depth; ++i) t += layer_proof_words(*c, i) * 4;
   return t;
@@ -807,6 +830,10 @@ int32_t gkr_prove_layer(const gkr_circuit* c, uint32_t layer, const gkr_fr* d_ne
     set_error("bad circuit or layer");
     return GKR_EINVAL;
   }
+  if (c->general) {
+    set_error("gkr_prove_layer takes layered circuits only (a general circuit's layers share claims)");
+    return GKR_EUNSUPPORTED;
+  }
   const bool first = layer == 0;
   const uint32_t si = c->s(layer), s1 = c->s(layer + 1);
   uint8_t* d_state = d_transcript ? d_transcript->state : nullptr;
@@ -876,9 +903,13 @@ int32_t gkr_prove_circuit(const gkr_circuit* c, const gkr_fr* d_inputs, uint64_t
   int32_t rc = check_ws(c, d_ws, ws_bytes);
   if (rc) return rc;
   try {
-    Workspace w = bind_workspace(*c, d_ws);
     Program pg;
-    emit_prove_circuit(pg, *c, w, d_inputs, seed, d_outputs, d_proof, current_tuning());
+    if (c->general) {
+      emit_prove_general(pg, *c, d_ws, d_inputs, seed, d_outputs, d_proof, current_tuning());
+    } else {
+      Workspace w = bind_workspace(*c, d_ws);
+      emit_prove_circuit(pg, *c, w, d_inputs, seed, d_outputs, d_proof, current_tuning());
+    }
     pg.run(static_cast<hipStream_t>(stream));
   } catch (const std::bad_alloc&) {
     set_error("host allocation failed");

@@ -42,6 +42,10 @@ int32_t gkr_plan_create(const gkr_job* job, gkr_plan** out) {
   }
   *out = nullptr;
   const gkr_circuit* c = job->circuit;
+  if (c->general) {
+    set_error("batch plans take layered circuits only");
+    return GKR_EUNSUPPORTED;
+  }
   if (!job->d_inputs || !job->d_outputs || !job->d_proof || !aligned16b(job->d_inputs) ||
       !aligned16b(job->d_outputs) || !aligned16b(job->d_proof)) {
     set_error("null or misaligned job buffer");

@@ -83,7 +83,18 @@ enum StepType : uint32_t {
   ST_LOCAL_VALUES,
   ST_STATE_EXPORT,
   ST_STATE_IMPORT,
-  ST_COUNT
+  ST_COUNT,
+  // General circuits (accumulation gates, right inputs from any later layer):
+  // launched by launch_general_step, plain path only.
+  ST_G_GATHER = 64,
+  ST_G_FORWARD,
+  ST_G_SCATTER,
+  ST_G_TTABLE,
+  ST_G_P1,
+  ST_G_P2,
+  ST_G_LAYER_BEGIN,
+  ST_G_VALUES,
+  ST_G_END
 };
 
 struct Step {
@@ -133,8 +144,14 @@ struct Plan {
 
 }  // namespace gkr
 
+namespace gkr {
+struct GeneralInfo;  // general circuits only (gkr_general.hip)
+}
+
 struct gkr_circuit {
   uint32_t depth = 0, n = 0;
+  gkr::GeneralInfo* general = nullptr;        // non-null for a general circuit
+  ~gkr_circuit();                             // frees the device block and the general description
   std::vector<uint32_t> sigma;                // [depth+1]
   std::vector<std::vector<gkr_gate>> gates;   // host copy of each layer's sub-circuit
   std::vector<uint64_t> mul_gates;            // MUL gates of each layer's sub-circuit
@@ -150,6 +167,10 @@ namespace gkr {
 
 void set_error(const std::string& msg);
 size_t plan_workspace(const gkr_circuit& c, Plan& p);
+// General circuits (gkr_general.hip, gkr_general_verify.cpp).
+void general_destroy(GeneralInfo* g);
+size_t general_proof_bytes(const gkr_circuit& c);
+size_t general_layer_proof_bytes(const gkr_circuit& c, uint32_t layer);
 Workspace bind_workspace(const gkr_circuit& c, void* base);
 uint32_t host_chal_index_rx(const gkr_circuit& c, uint32_t layer);  // index of rx[0] of a layer in chal
 uint32_t host_chal_index_ry(const gkr_circuit& c, uint32_t layer);

@@ -34,7 +34,9 @@ Sum g_sum[PC_COUNT];
 const char* kNames[PC_COUNT] = {"forward",        "digest",         "transcript",    "eq_tables",
                                 "output_claim",   "phase1_init",    "round",         "round_sub",
                                 "tail",           "tail_sub",       "phase2_tables", "copy_contract",
-                                "local_contract", "small",          "convert",       "batch"};
+                                "local_contract", "small",          "convert",       "batch",
+                                "g_gather",       "g_forward",      "g_claim_tables", "g_phase1_init",
+                                "g_phase2_tables"};
 
 hipEvent_t get_event() {
   if (!g_pool.empty()) {

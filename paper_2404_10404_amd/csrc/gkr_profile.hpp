@@ -22,6 +22,11 @@ enum ProfClass {
   PC_SMALL,
   PC_CONVERT,
   PC_BATCH,
+  PC_G_GATHER,
+  PC_G_FORWARD,
+  PC_G_CLAIMS,
+  PC_G_PHASE1_INIT,
+  PC_G_PHASE2_TABLES,
   PC_COUNT
 };
 

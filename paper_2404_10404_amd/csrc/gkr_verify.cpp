@@ -12,10 +12,12 @@
 // variables (and Cv likewise), so a layer costs O(2^sigma + n).
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <thread>
 #include <vector>
 
+#include "gkr_general.hpp"
 #include "gkr_internal.hpp"
 
 namespace gkr {
@@ -173,6 +175,174 @@ bool canonical_all(const void* p, uint64_t count) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------- general circuits
+
+namespace {
+
+// A claim the verifier holds about a layer (values and points in Montgomery form).
+struct HClaim {
+  bool subset;
+  std::vector<Fr> point;                 // eq: s_j entries; subset: tau + n entries
+  Fr value;
+  uint32_t tau;                          // subset: bits of the local part
+  const std::vector<uint32_t>* used;     // subset: the used gates
+};
+
+// Local weights of a claim over a layer's sub-circuit, scaled by `coef`:
+// eq: coef eq(point[:sigma], z); subset: coef eq(point[:tau], k) at z = used[k].
+std::vector<Fr> claim_local(const HClaim& cl, uint32_t sigma, const Fr& coef) {
+  std::vector<Fr> L;
+  if (!cl.subset) {
+    L = eq_table_host(cl.point.data(), sigma);
+    for (Fr& v : L) v = fr_mul(v, coef);
+  } else {
+    L.assign(1ull << sigma, fr_zero());
+    const std::vector<Fr> e = eq_table_host(cl.point.data(), cl.tau);
+    for (size_t k = 0; k < cl.used->size(); ++k) L[(*cl.used)[k]] = fr_mul(e[k], coef);
+  }
+  return L;
+}
+
+const Fr* claim_copy_point(const HClaim& cl, uint32_t sigma) {
+  return cl.point.data() + (cl.subset ? cl.tau : sigma);
+}
+
+}  // namespace
+
+// The general-circuit verifier: the layered checks (rounds, final predicate,
+// inputs) plus, per layer, the concatenation identity vy = sum_b eq(r_y[:beta],
+// b) v_b, with every block value becoming a claim on its source layer. The
+// predicates factor the copy bits as in the layered verifier: with local
+// weights L_k and copy point c_k of claim k,
+//   mult~ = sum_k triple(c_k, rx_copy, ry_copy) sum_{MUL} L_k[z] eqL(rx, x) eqL(ry, y').
+int32_t general_verify(const gkr_circuit& c, const gkr_fr* inputs, const gkr_fr* outputs, uint64_t seed,
+                       const uint8_t* proof, size_t proof_len) {
+  const GeneralInfo& g = *c.general;
+  const uint32_t d = c.depth, n = c.n;
+  const size_t need = general_proof_bytes(c);
+  if (proof_len != need) {
+    set_error("proof length " + std::to_string(proof_len) + ", expected " + std::to_string(need));
+    return GKR_EINVAL;
+  }
+  const uint64_t nin = 1ull << c.s(d), nout = 1ull << c.s(0);
+  if (!canonical_all(inputs, nin) || !canonical_all(outputs, nout) || !canonical_all(proof, need / 32)) {
+    set_error("element not canonical");
+    return GKR_EINVAL;
+  }
+  const Fr* pf = reinterpret_cast<const Fr*>(proof);
+  uint64_t pos = 0;
+  HostTranscript tr;
+  {
+    uint8_t msg[19];
+    memcpy(msg, "SISU-GKR-v1", 11);
+    for (int k = 0; k < 8; ++k) msg[11 + k] = (uint8_t)(seed >> (8 * k));
+    sha256_bytes(msg, sizeof(msg), tr.st.h);
+  }
+  uint32_t dig[8];
+  tr.absorb_words(kTagDigest, c.digest, 8);
+  tree_digest_host(reinterpret_cast<const uint8_t*>(inputs), nin * 32, dig);
+  tr.absorb_words(kTagDigest, dig, 8);
+  tree_digest_host(reinterpret_cast<const uint8_t*>(outputs), nout * 32, dig);
+  tr.absorb_words(kTagDigest, dig, 8);
+
+  std::vector<std::vector<HClaim>> pending(d + 1);
+  {
+    HClaim cl{false, std::vector<Fr>(c.s(0)), fr_zero(), 0, nullptr};
+    for (auto& x : cl.point) x = to_m(tr.squeeze());
+    cl.value = mle_host(outputs, c.s(0), cl.point.data());
+    pending[0].push_back(cl);
+  }
+  bool accept = true;
+  auto phase = [&](uint32_t rounds, Fr& claim, std::vector<Fr>& rs) {
+    for (uint32_t j = 0; j < rounds; ++j) {
+      const Fr* e = pf + pos;
+      pos += 3;
+      const Fr e0 = to_m(e[0]), e1 = to_m(e[1]), e2 = to_m(e[2]);
+      if (!fr_eq(fr_add(e0, e1), claim)) accept = false;
+      const Fr r = to_m(tr.round_challenge(e));
+      rs.push_back(r);
+      claim = fr_interp3(e0, e1, e2, r);
+    }
+  };
+  for (uint32_t i = 0; i < d; ++i) {
+    const GeneralLayer& L = g.layers[i];
+    const std::vector<HClaim>& claims = pending[i];
+    std::vector<Fr> coef(claims.size(), fr_one());
+    if (i > 0)
+      for (auto& a : coef) a = to_m(tr.squeeze());
+    Fr claim = fr_zero();
+    for (size_t k = 0; k < claims.size(); ++k) claim = fr_add(claim, fr_mul(coef[k], claims[k].value));
+    const uint32_t s1 = c.s(i + 1), rho = g.rho(i), sg = c.sigma[i], sg1 = c.sigma[i + 1];
+    std::vector<Fr> rx, ry;
+    phase(s1, claim, rx);
+    const Fr vx = to_m(pf[pos]);
+    tr.absorb_elements(kTagValue, pf + pos, 1);
+    ++pos;
+    phase(rho, claim, ry);
+    const Fr vy = to_m(pf[pos]);
+    tr.absorb_elements(kTagValue, pf + pos, 1);
+    ++pos;
+    std::vector<Fr> vals;
+    for (size_t b = 0; b < L.sources.size(); ++b) {
+      vals.push_back(to_m(pf[pos]));
+      tr.absorb_elements(kTagValue, pf + pos, 1);
+      ++pos;
+    }
+    // concatenation identity
+    {
+      const std::vector<Fr> eb = eq_table_host(ry.data(), L.beta);
+      Fr s = fr_zero();
+      for (size_t b = 0; b < vals.size(); ++b) s = fr_add(s, fr_mul(eb[b], vals[b]));
+      if (!fr_eq(s, vy)) accept = false;
+    }
+    // predicates: per-gate weight W[z] = sum_k triple_k L_k[z]
+    std::vector<Fr> W(1ull << sg, fr_zero());
+    for (size_t k = 0; k < claims.size(); ++k) {
+      const std::vector<Fr> Lk = claim_local(claims[k], sg, coef[k]);
+      const Fr t = triple_eq(claim_copy_point(claims[k], sg), rx.data() + sg1, ry.data() + rho - n, n);
+      for (size_t z = 0; z < W.size(); ++z) W[z] = fr_add(W[z], fr_mul(t, Lk[z]));
+    }
+    const std::vector<Fr> elx = eq_table_host(rx.data(), sg1), ely = eq_table_host(ry.data(), rho - n);
+    Fr add_v = fr_zero(), mul_v = fr_zero();
+    for (const gkr_nested_gate& r : L.recs) {
+      const size_t b = std::find(L.sources.begin(), L.sources.end(), r.src) - L.sources.begin();
+      const std::vector<uint32_t>& u = L.used[b];
+      const uint32_t k = (uint32_t)(std::lower_bound(u.begin(), u.end(), r.y) - u.begin());
+      const uint32_t yl = ((uint32_t)b << L.tau) | k;
+      const Fr term = fr_mul(fr_mul(W[r.z], elx[r.x]), ely[yl]);
+      if (r.type == GKR_GATE_MUL) mul_v = fr_add(mul_v, term);
+      else add_v = fr_add(add_v, term);
+    }
+    const Fr fin = fr_add(fr_mul(fr_mul(mul_v, vx), vy), fr_mul(add_v, fr_add(vx, vy)));
+    if (!fr_eq(fin, claim)) accept = false;
+    pending[i + 1].push_back(HClaim{false, rx, vx, 0, nullptr});
+    for (size_t b = 0; b < L.sources.size(); ++b)
+      pending[L.sources[b]].push_back(
+          HClaim{true, std::vector<Fr>(ry.begin() + L.beta, ry.end()), vals[b], L.tau, &L.used[b]});
+  }
+  // the input layer: every claim straight from the inputs
+  for (const HClaim& cl : pending[d]) {
+    if (!accept) break;
+    Fr want;
+    if (!cl.subset) {
+      want = mle_host(inputs, c.s(d), cl.point.data());
+    } else {
+      const std::vector<Fr> el = eq_table_host(cl.point.data(), cl.tau);
+      const std::vector<Fr> ec = eq_table_host(cl.point.data() + cl.tau, n);
+      want = fr_zero();
+      for (size_t k = 0; k < cl.used->size(); ++k) {
+        Fr s = fr_zero();
+        for (uint64_t cp = 0; cp < (1ull << n); ++cp)
+          s = fr_add(s, fr_mul(ec[cp], to_m(*reinterpret_cast<const Fr*>(&inputs[((uint64_t)(*cl.used)[k] << n) | cp]))));
+        want = fr_add(want, fr_mul(el[k], s));
+      }
+    }
+    if (!fr_eq(want, cl.value)) accept = false;
+  }
+  return accept ? 1 : 0;
+}
+
 }  // namespace gkr
 
 using namespace gkr;
@@ -184,6 +354,7 @@ extern "C" int32_t gkr_verify(const gkr_circuit* c, const gkr_fr* inputs, const 
       set_error("null argument");
       return GKR_EINVAL;
     }
+    if (c->general) return general_verify(*c, inputs, outputs, seed, proof, proof_len);
     const uint32_t d = c->depth, n = c->n;
     size_t need = 0;
     for (uint32_t i = 0; i < d; ++i) need += (6ull * c->s(i + 1) + 2) * 32;

@@ -30,7 +30,7 @@ EXPORTS = (
     "gkr_transcript_init", "gkr_output_claim", "gkr_prove_layer", "gkr_verify",
     "gkr_plan_create", "gkr_plan_destroy", "gkr_plan_reset", "gkr_run_batch", "gkr_plan_progress",
     "gkr_prove_batch", "gkr_set_tuning", "gkr_get_tuning", "gkr_profile_enable", "gkr_profile_read",
-    "gkr_ubench", "gkr_prove_circuit_noalloc",
+    "gkr_ubench", "gkr_prove_circuit_noalloc", "gkr_general_circuit_create",
 )
 
 # Size of the static workspace of gkr_prove_circuit_noalloc (GKR_NOALLOC_WORKSPACE_BYTES).
@@ -49,6 +49,13 @@ class Gate(ctypes.Structure):
     endian, type < 256)."""
     _fields_ = [("x", ctypes.c_uint32), ("y", ctypes.c_uint32), ("type", ctypes.c_uint8),
                 ("reserved", ctypes.c_uint8 * 3)]
+
+
+class NestedGate(ctypes.Structure):
+    """gkr_nested_gate: z, x, src, y (u32), type (u8), three reserved bytes. A
+    (count, 5) uint32 array with the type in the fifth word has this layout."""
+    _fields_ = [("z", ctypes.c_uint32), ("x", ctypes.c_uint32), ("src", ctypes.c_uint32), ("y", ctypes.c_uint32),
+                ("type", ctypes.c_uint8), ("reserved", ctypes.c_uint8 * 3)]
 
 
 _lib = None
@@ -71,6 +78,9 @@ def lib() -> ctypes.CDLL:
         L.gkr_circuit_create.argtypes = [_u32, _u32, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.POINTER(Gate)),
                                          ctypes.POINTER(_vp)]
         L.gkr_circuit_create.restype = _i32
+        L.gkr_general_circuit_create.argtypes = [_u32, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_u64),
+                                                 ctypes.POINTER(ctypes.POINTER(NestedGate)), ctypes.POINTER(_vp)]
+        L.gkr_general_circuit_create.restype = _i32
         L.gkr_circuit_destroy.argtypes = [_vp]
         L.gkr_circuit_destroy.restype = None
         for name in ("gkr_workspace_bytes", "gkr_proof_bytes"):
@@ -200,6 +210,34 @@ class Circuit:
     @property
     def gate_layers(self) -> int:
         return lib().gkr_gate_layers(self._h)
+
+
+class GeneralCircuit(Circuit):
+    """A general circuit (nested gates with right inputs from any later layer)."""
+
+    def __init__(self, depth: int, log_copies: int, log_sub_width: Sequence[int],
+                 layers: Sequence[Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray, np.ndarray]]):
+        L = lib()
+        self.depth, self.log_copies = int(depth), int(log_copies)
+        self.log_sub_width = [int(s) for s in log_sub_width]
+        sig = (_u32 * len(self.log_sub_width))(*self.log_sub_width)
+        arrays = []
+        counts = (_u64 * max(1, len(layers)))()
+        ptrs = (ctypes.POINTER(NestedGate) * max(1, len(layers)))()
+        for i, (z, x, src, y, t) in enumerate(layers):
+            g = np.empty((len(z), 5), dtype=np.uint32)
+            g[:, 0], g[:, 1], g[:, 2], g[:, 3], g[:, 4] = z, x, src, y, t
+            arrays.append(g)
+            counts[i] = len(z)
+            ptrs[i] = g.ctypes.data_as(ctypes.POINTER(NestedGate))
+        h = _vp()
+        _check(L.gkr_general_circuit_create(self.depth, self.log_copies, sig, counts, ptrs, ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_synth(cls, spec, wiring) -> "GeneralCircuit":
+        return cls(spec.depth, spec.log_copies, spec.log_sub_width,
+                   [(w.z, w.x, w.src, w.y, w.kind) for w in wiring])
 
 
 # ------------------------------------------------------------ device-level calls

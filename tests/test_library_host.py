@@ -133,3 +133,62 @@ def test_build_refuses_register_spills():
     ])
     assert build._vgpr_spills(remarks) == [("_ZN3gkr7k_batchENS_9BatchArgsE", 0), ("_ZN3gkr8k_tail_aENS_4StepE", 3)]
     assert build._vgpr_spills("no remarks here") == []
+
+
+def _general_case(depth, n, sig, seed, fanin=3, reach=3):
+    from oracle import general as og
+    spec = gs.GeneralSpec(depth=depth, log_copies=n, log_sub_width=tuple(sig), max_fanin=fanin, reach=reach,
+                          cross=(1, 2), seed=seed)
+    wiring = gs.make_general_wiring(spec)
+    inputs = gs.make_general_inputs(spec)
+    oc_ = og.GeneralCircuit.from_synth(spec, wiring)
+    pt = og.prove(oc_, gs.elements_to_ints(inputs), seed)
+    return spec, wiring, inputs, oc_, pt
+
+
+@pytest.mark.parametrize("shape", [
+    (2, 0, (2, 3, 2), 11),
+    (4, 2, (2, 3, 3, 2, 3), 12),
+    (3, 3, (0, 2, 1, 2), 13),
+    (5, 1, (3, 3, 4, 3, 2, 3), 14),
+    (1, 0, (0, 0), 15),
+])
+def test_host_verifier_accepts_oracle_general_proofs(shape):
+    """The library's general-circuit object (digest, used-gate blocks, proof
+    length) and host verifier agree with the oracle: its proofs are accepted,
+    tampered ones rejected."""
+    depth, n, sig, seed = shape
+    spec, wiring, inputs, oc_, pt = _general_case(depth, n, sig, seed, fanin=4, reach=4)
+    c = gkr.GeneralCircuit.from_synth(spec, wiring)
+    assert c.proof_bytes == len(pt.proof_bytes())
+    assert c.gate_layers == spec.gate_layers
+    outs = gs.ints_to_elements(pt.outputs)
+    proof = pt.proof_bytes()
+    assert gkr.verify(c, inputs, outs, seed, proof) == 1
+    if spec.log_width(0) + sum(oc_.s(i + 1) + oc_.rho(i) for i in range(depth)) > 0:
+        # (a circuit with no challenge at all has a seed-independent proof)
+        assert gkr.verify(c, inputs, outs, seed + 1, proof) == 0
+    for k in range(0, len(proof) // 32, 3):
+        bad = bytearray(proof)
+        bad[32 * k] ^= 1
+        assert gkr.verify(c, inputs, outs, seed, bytes(bad)) in (0, gkr.GKR_EINVAL), k
+    bad_in = inputs.copy()
+    bad_in[-1, 0] ^= 1
+    assert gkr.verify(c, bad_in, outs, seed, proof) in (0, gkr.GKR_EINVAL)
+
+
+def test_general_circuit_validation():
+    z = np.zeros(1, dtype=np.uint32)
+    with pytest.raises(gkr.GkrError):  # right input from the same layer
+        gkr.GeneralCircuit(1, 0, [0, 1], [(z, z, z, z, z)])
+    with pytest.raises(gkr.GkrError):  # left input out of range
+        gkr.GeneralCircuit(1, 0, [0, 1], [(z, z + 2, z + 1, z, z)])
+    with pytest.raises(gkr.GkrError):  # no nested gates in a layer
+        e = np.zeros(0, dtype=np.uint32)
+        gkr.GeneralCircuit(1, 0, [0, 1], [(e, e, e, e, e)])
+    ok = gkr.GeneralCircuit(1, 0, [0, 1], [(z, z, z + 1, z + 1, z)])
+    assert ok.proof_bytes == (3 * 1 + 3 * 0 + 2 + 1) * 32
+
+
+def test_abi_struct_sizes():
+    assert ctypes.sizeof(gkr.Gate) == 12 and ctypes.sizeof(gkr.NestedGate) == 20
