@@ -95,7 +95,9 @@ def profile_pass(gkr, prover, d_in, seed, steps):
 # Profile class -> kernel, for the traffic records taken with rocprofv3 --pmc.
 CLASS_KERNEL = {"round": "k_round_a", "round_sub": "k_round_b", "tail": "k_tail_a", "tail_sub": "k_tail_b",
                 "phase1_init": "k_p1_init_round", "forward": "k_forward", "copy_contract": "k_copy_contract",
-                "local_contract": "k_local_contract", "digest": "k_digest"}
+                "local_contract": "k_local_contract", "digest": "k_digest", "g_gather": "k_g_gather",
+                "g_forward": "k_g_forward", "g_claim_tables": "k_g_ttable", "g_phase1_init": "k_g_p1",
+                "g_phase2_tables": "k_g_p2"}
 KERNEL_SOURCES = ["fr.hpp", "sha256.hpp", "gkr_device.hpp", "gkr_kernels.hpp", "gkr_bodies.hpp", "gkr_kernels.hip"]
 
 
@@ -317,6 +319,44 @@ def serving_comparison(gkr, njobs, max_slots, budget_gib, util=0.8):
     }
 
 
+def general_leg(gkr, steps, warmup, profile_steps, mac_peak_tops):
+    """The general-circuit workload (accumulation gates, right inputs from up to
+    four layers back): field-gates/s and nested-gates/s of plain proofs, the
+    proof against the oracle's digest, the dominant kernel's roofline."""
+    import torch
+    spec = gs.general_data_parallel()
+    wiring = gs.make_general_wiring(spec)
+    inputs = gs.make_general_inputs(spec)
+    c = gkr.GeneralCircuit.from_synth(spec, wiring)
+    nested = sum(len(w.z) for w in wiring) << spec.log_copies
+    prover = gkr.Prover(c)
+    d_in = gkr.device_elements(inputs)
+    del inputs
+    for _ in range(warmup):
+        prover.prove(d_in, spec.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prover.prove(d_in, spec.seed)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    out = {"workload": "general circuit: 2^8 copies x (depth 8, 2^12 gates/layer), 1..4 nested gates per gate, "
+                       "a quarter of the right inputs from 2..4 layers back",
+           "gate_layers_per_proof": c.gate_layers, "nested_gates_per_proof": nested,
+           "ms_per_proof": round(dt * 1e3, 4), "field_gates_per_s": round(c.gate_layers / dt, 1),
+           "nested_gates_per_s": round(nested / dt, 1)}
+    gd = golden_digest("g1")
+    if gd is not None:
+        out["bit_exact_vs_oracle_golden"] = hashlib.sha256(prover.proof_bytes()).hexdigest() == gd
+    if profile_steps:
+        prof = profile_pass(gkr, prover, d_in, spec.seed, profile_steps)
+        out["roofline"] = roofline(prof, "g1", mac_peak_tops)
+        out["kernels"] = {k: {"ms": round(v["ms"], 4), "launches": v["launches"]} for k, v in
+                          sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:8]}
+    del prover, d_in
+    return out
+
+
 def golden_digest(name):
     p = os.path.join(ROOT, "tests", "golden", "%s_proof.json" % name)
     if not os.path.exists(p):
@@ -353,6 +393,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="leave out the 64-job batched leg")
     ap.add_argument("--no-serving", action="store_true", help="leave out the serving leg")
+    ap.add_argument("--no-general", action="store_true", help="leave out the general-circuit leg")
     ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serving", "copy", "ubench"])
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--jobs", type=int, default=256)
@@ -470,6 +511,12 @@ def main():
     if args.workload == "c3":
         log("c3: the same sub-circuit with 2^4 copies against the oracle's proof")
         exact["c3_slice_2^4_copies_vs_oracle_golden"] = slice_bit_exact(gkr, spec, 4, "c3slice")
+        torch.cuda.empty_cache()
+    if not args.no_general:
+        log("general-circuit leg")
+        line["general"] = general_leg(gkr, 5, 1, 0 if args.no_profile else 1,
+                                      peaks["mad_u64_u32_per_s"] / 1e12 if peaks else None)
+        exact["general_vs_oracle_golden"] = line["general"].get("bit_exact_vs_oracle_golden")
         torch.cuda.empty_cache()
     if not args.no_batched:
         log("batched leg: 64 uneven jobs")

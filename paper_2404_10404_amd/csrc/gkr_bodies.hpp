@@ -407,14 +407,22 @@ __device__ __forceinline__ void body_p1_init(const Step& st, uint32_t tile, uint
 }
 
 // ST_P1_INIT_ROUND: the tables and the first round together: b builds entries
-// b and b + half and evaluates the round-1 pair at t = 0, 2.
+// b and b + half and evaluates the round-1 pair at t = 0, 2. With Lazy the
+// t = 0 products of a thread's pairs are summed unreduced (a 512-bit
+// accumulator, one reduction per 16 pairs; a thread takes many pairs here; a
+// second accumulator for t = 2 would not fit the registers of three
+// workgroups per CU); the batch kernel, which holds every body, takes the
+// reduced form (Lazy = false) to stay within its registers.
 // q0 half; p9 S, p10 partials, p11 r_out, p12 msg.
+template <bool Lazy>
 __device__ __forceinline__ void body_p1_init_round(const Step& st, uint32_t tile, uint32_t ntiles) {
   const Fr* W = P<const Fr*>(st, 0);
   Fr* G = P<Fr*>(st, 1);
   Fr* H = P<Fr*>(st, 2);
   const uint64_t half = st.q[0];
   Fr acc[2] = {fr_zero(), fr_zero()};
+  FrWide e0 = frw_zero();
+  uint32_t lazy = 0;
   for (uint64_t b = GTID; b < half; b += GSTRIDE) {
     Fr g0, h0, g1, h1;
     phase1_entry(st, b, g0, h0);
@@ -424,10 +432,22 @@ __device__ __forceinline__ void body_p1_init_round(const Step& st, uint32_t tile
     stf(G, b + half, g1);
     stf(H, b + half, h1);
     const Fr w0 = ldf(W, b), w1 = ldf(W, b + half);
-    acc[0] = fr_add(acc[0], fr_add(fr_mul(w0, g0), h0));
     const Fr w2 = fr_sub(fr_double(w1), w0), g2 = fr_sub(fr_double(g1), g0), h2 = fr_sub(fr_double(h1), h0);
+    if constexpr (!Lazy) {
+      acc[0] = fr_add(acc[0], fr_add(fr_mul(w0, g0), h0));
+      acc[1] = fr_add(acc[1], fr_add(fr_mul(w2, g2), h2));
+      continue;
+    }
+    frw_mac(e0, w0, g0);
+    acc[0] = fr_add(acc[0], h0);
     acc[1] = fr_add(acc[1], fr_add(fr_mul(w2, g2), h2));
+    if (++lazy == 16) {
+      acc[0] = fr_add(acc[0], frw_reduce<16>(e0));
+      e0 = frw_zero();
+      lazy = 0;
+    }
   }
+  if (lazy) acc[0] = fr_add(acc[0], frw_reduce<16>(e0));
   write_partial<2>(acc, P<Fr*>(st, 10), tile);
 }
 
@@ -1037,7 +1057,7 @@ __device__ __forceinline__ void run_step_tile(const Step& st, uint32_t tile, uin
       break;
     case ST_P1_INIT: body_p1_init(st, tile, ntiles); break;
     case ST_P1_INIT_ROUND:
-      body_p1_init_round(st, tile, ntiles);
+      body_p1_init_round<false>(st, tile, ntiles);
       if (last_tile(counter, ntiles)) finish_p1_init_round(st, ntiles);
       break;
     case ST_ROUND_A:

@@ -48,7 +48,7 @@ __device__ __forceinline__ void run_step_tile_wsum(const Step& st, uint32_t t, u
   if (last_tile(&P<DevState*>(st, 4)->counter, n)) finish_wsum(st, n);
 }
 __device__ __forceinline__ void run_step_tile_p1_init_round(const Step& st, uint32_t t, uint32_t n) {
-  body_p1_init_round(st, t, n);
+  body_p1_init_round<true>(st, t, n);
   if (last_tile(&P<DevState*>(st, 9)->counter, n)) finish_p1_init_round(st, n);
 }
 __device__ __forceinline__ void run_step_tile_round_a(const Step& st, uint32_t t, uint32_t n) {

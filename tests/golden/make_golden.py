@@ -5,7 +5,11 @@ workload, the SHA-256 of the outputs and of the proof, and the proof itself
 (hex) for the smaller cases. "c4" proves the 64 jobs of the uneven batch
 (one oracle process per CPU) and stores each job's digests.
 
-    python tests/golden/make_golden.py c1 c2 c3slice c4
+    python tests/golden/make_golden.py c1 c2 c3slice c4 g1slice g1
+
+"g1" is the general-circuit workload (accumulation gates, right inputs from
+up to four layers back, oracle/general.py); "g1slice" the same sub-circuit
+with 2^2 copies.
 """
 import hashlib
 import json
@@ -17,8 +21,11 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
+import dataclasses  # noqa: E402
+
 import gkr_synth as gs  # noqa: E402
 from oracle import circuit as oc  # noqa: E402
+from oracle import general as og  # noqa: E402
 from oracle import prover as op  # noqa: E402
 from oracle.field import encode_all  # noqa: E402
 
@@ -30,7 +37,39 @@ CASES = {
 }
 
 
+GENERAL_CASES = {
+    "g1": (gs.general_data_parallel, False),
+    "g1slice": (lambda: dataclasses.replace(gs.general_data_parallel(), log_copies=2), True),
+}
+
+
+def make_general(name):
+    spec = GENERAL_CASES[name][0]()
+    t0 = time.time()
+    wiring = gs.make_general_wiring(spec)
+    inputs = gs.elements_to_ints(gs.make_general_inputs(spec))
+    pt = og.prove(og.GeneralCircuit.from_synth(spec, wiring), inputs, spec.seed)
+    proof = pt.proof_bytes()
+    rec = {
+        "workload": name, "depth": spec.depth, "log_copies": spec.log_copies,
+        "log_sub_width": list(spec.log_sub_width), "max_fanin": spec.max_fanin, "reach": spec.reach,
+        "cross": list(spec.cross), "mu": list(spec.mu), "seed": spec.seed,
+        "outputs_sha256": hashlib.sha256(encode_all(pt.outputs)).hexdigest(),
+        "proof_sha256": hashlib.sha256(proof).hexdigest(),
+        "proof_len": len(proof),
+        "oracle_seconds": round(time.time() - t0, 1),
+        "writer": "tests/golden/make_golden.py (CPU oracle)",
+    }
+    if GENERAL_CASES[name][1]:
+        rec["proof_hex"] = proof.hex()
+    with open(os.path.join(HERE, "%s_proof.json" % name), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(name, "done in %.1f s" % (time.time() - t0), flush=True)
+
+
 def make(name):
+    if name in GENERAL_CASES:
+        return make_general(name)
     spec = CASES[name][0]()
     t0 = time.time()
     wiring = gs.make_wiring(spec)

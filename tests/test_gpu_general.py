@@ -4,6 +4,10 @@ later layer): outputs and proof bytes of the HIP path equal the oracle's
 accepts them. Shapes cover one copy and many, fan-in 1 (no accumulation) to 4,
 right inputs from the next layer only and from up to four layers back, tables
 inside the single-workgroup tail and grid-wide rounds in both phases."""
+import dataclasses
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
@@ -101,3 +105,38 @@ def test_general_no_alloc_and_repeat(gkr):
     assert bytes(proof[: c.proof_bytes].cpu().numpy().tobytes()) == a
     ref = og.prove(og.GeneralCircuit.from_synth(spec, wiring), gs.elements_to_ints(inputs), spec.seed)
     assert a == ref.proof_bytes()
+
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.mark.parametrize("name,log_copies", [("g1slice", 2), ("g1", 8)])
+def test_general_workload_matches_oracle_golden(gkr, name, log_copies):
+    """The general-circuit workload bench.py times (2^8 copies x depth 8, 2^12
+    gates/layer, up to 4 nested gates) and its 2^2-copy slice, against the
+    oracle's stored digests (tests/golden/make_golden.py); the host verifier
+    accepts the full-size proof."""
+    import torch
+    path = os.path.join(HERE, "golden", "%s_proof.json" % name)
+    with open(path) as f:
+        gold = json.load(f)
+    spec = dataclasses.replace(gs.general_data_parallel(), log_copies=log_copies)
+    assert gold["seed"] == spec.seed and gold["log_copies"] == spec.log_copies
+    _log("general golden %s: proving" % name)
+    wiring = gs.make_general_wiring(spec)
+    inputs = gs.make_general_inputs(spec)
+    c = gkr.GeneralCircuit.from_synth(spec, wiring)
+    pr = gkr.Prover(c)
+    pr.prove(gkr.device_elements(inputs), spec.seed)
+    torch.cuda.synchronize()
+    proof = pr.proof_bytes()
+    outs = np.ascontiguousarray(gkr.host_elements(pr.outputs))
+    assert hashlib.sha256(outs.tobytes()).hexdigest() == gold["outputs_sha256"]
+    if hashlib.sha256(proof).hexdigest() != gold["proof_sha256"]:
+        if "proof_hex" in gold:
+            ref = bytes.fromhex(gold["proof_hex"])
+            first = next(i for i in range(len(ref)) if ref[i] != proof[i])
+            raise AssertionError("proof differs from the oracle's at element %d" % (first // 32))
+        raise AssertionError("proof digest differs from the oracle's")
+    _log("general golden %s: host verifier" % name)
+    assert gkr.verify(c, inputs, outs, spec.seed, proof) == 1
