@@ -398,3 +398,39 @@ def general_data_parallel() -> GeneralSpec:
     gates per gate (accumulation gates), a quarter of the right inputs from 2..4 layers back."""
     return GeneralSpec(depth=8, log_copies=8, log_sub_width=(12,) * 9, max_fanin=4, reach=4, cross=(1, 4),
                        mu=(1, 2), seed=41)
+
+
+# ---------------------------------------------------------------- Goldilocks elements
+
+GOLDILOCKS = (1 << 64) - (1 << 32) + 1  # the modulus (element range for rejection sampling only)
+
+
+def goldilocks_elements(key: int, count: int, start: int = 0) -> np.ndarray:
+    """Uniform canonical Goldilocks elements start..start+count-1 of the element
+    stream `key`: element k takes output a of its own sub-stream (state
+    stream_at(key, k)) for attempt a = 0, 1, ... and accepts the first value
+    below the modulus (acceptance 1 - 2^-32 per attempt). uint64 array."""
+    out = np.zeros(count, dtype=np.uint64)
+    if count == 0:
+        return out
+    sub = stream(key, count, start)
+    pending = np.arange(count, dtype=np.int64)
+    attempt = 0
+    with np.errstate(over="ignore"):
+        while pending.size:
+            w = _mix64_np(sub[pending] + np.uint64(((attempt + 1) * GAMMA) & _M64))
+            ok = w < np.uint64(GOLDILOCKS)
+            out[pending[ok]] = w[ok]
+            pending = pending[~ok]
+            attempt += 1
+    return out
+
+
+def make_goldilocks_inputs(spec: CircuitSpec, start: int = 0, count: Optional[int] = None) -> np.ndarray:
+    """Input layer V_d of a layered circuit over the Goldilocks field (uint64)."""
+    total = 1 << spec.log_width(spec.depth)
+    if count is None:
+        count = total - start
+    if start < 0 or start + count > total:
+        raise ValueError("input slice out of range")
+    return goldilocks_elements(stream_key(spec.seed, PURPOSE_INPUT, 0), count, start)

@@ -14,4 +14,4 @@ FIPS 180-4 vectors), eq/MLE identities, brute-force hypercube sums of every
 round polynomial on tiny circuits, the per-round invariant g_j(0)+g_j(1) =
 claim, verifier acceptance and tamper rejection pin each part; see the tests.
 """
-from . import field, mle, transcript, circuit, prover, verifier, general  # noqa: F401
+from . import field, mle, transcript, circuit, prover, verifier, general, goldilocks  # noqa: F401
