@@ -131,17 +131,19 @@ def traffic_record(kernel, workload):
     return None
 
 
-def roofline(prof, workload=None, mac_peak_tops=None):
+def roofline(prof, workload=None, mac_peak_tops=None, macs_per_mulmod=MACS_PER_MULMOD):
     """Roofline of the dominant kernel class: t_roof = max(bytes / HBM peak,
     multiply-adds / integer-multiply peak); the bound is the larger term.
-    The integer peak is the measured v_mad_u64_u32 rate when given."""
+    The integer peak is the measured v_mad_u64_u32 rate when given; a field
+    product counts macs_per_mulmod 32x32 multiply-adds (136 for BN254's
+    8-limb Montgomery product, 4 for a Goldilocks 64 x 64 product)."""
     name, e = max(prof.items(), key=lambda kv: kv[1]["ms"])
     sec = e["ms"] / 1e3
     gbs = e["bytes"] / sec / 1e9
-    tops = e["mulmods"] * MACS_PER_MULMOD / sec / 1e12
+    tops = e["mulmods"] * macs_per_mulmod / sec / 1e12
     alu_peak = mac_peak_tops if mac_peak_tops else VALU_PEAK_TOPS
     t_hbm = e["bytes"] / (HBM_PEAK_GBS * 1e9)
-    t_alu = e["mulmods"] * MACS_PER_MULMOD / (alu_peak * 1e12)
+    t_alu = e["mulmods"] * macs_per_mulmod / (alu_peak * 1e12)
     if t_hbm >= t_alu:
         r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": round(gbs / HBM_PEAK_GBS, 4)}
@@ -357,6 +359,48 @@ def general_leg(gkr, steps, warmup, profile_steps, mac_peak_tops):
     return out
 
 
+def goldilocks_leg(gkr, steps, warmup, profile_steps, mac_peak_tops, bn254_ms=None):
+    """The single-worker share (2^12 copies x depth 24 x 2^14 gates/layer) over
+    the Goldilocks field (Section 4.1): field-gates/s, the speed-up over the
+    BN254 proof, its 2^4-copy slice against the oracle's digest, the dominant
+    kernel's roofline."""
+    import torch
+    spec = gs.worker_share_c3()
+    wiring = gs.make_wiring(spec)
+    c = gkr.Circuit.from_synth(spec, wiring, field=gkr.FIELD_GOLDILOCKS)
+    prover = gkr.GlProver(c)
+    d_in = gkr.gl_device_elements(gs.make_goldilocks_inputs(spec))
+    for _ in range(warmup):
+        prover.prove(d_in, spec.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prover.prove(d_in, spec.seed)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    out = {"workload": "Goldilocks field, single-worker share: 2^12 copies x (depth 24, 2^14 gates/layer), 30% MUL",
+           "gate_layers_per_proof": c.gate_layers, "ms_per_proof": round(dt * 1e3, 4),
+           "field_gates_per_s": round(c.gate_layers / dt, 1)}
+    if bn254_ms:
+        out["speedup_vs_bn254"] = round(bn254_ms / (dt * 1e3), 2)
+    if profile_steps:
+        prof = profile_pass(gkr, prover, d_in, spec.seed, profile_steps)
+        out["roofline"] = roofline(prof, "gl_c3", mac_peak_tops, macs_per_mulmod=4)
+        out["kernels"] = {k: {"ms": round(v["ms"], 4), "launches": v["launches"]} for k, v in
+                          sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:8]}
+    del prover, d_in
+    torch.cuda.empty_cache()
+    gd = golden_digest("gl_c3slice")
+    if gd is not None:
+        sl = gs.copy_slice(spec, 4)
+        cs = gkr.Circuit.from_synth(sl, gs.make_wiring(sl), field=gkr.FIELD_GOLDILOCKS)
+        ps = gkr.GlProver(cs)
+        ps.prove(gkr.gl_device_elements(gs.make_goldilocks_inputs(sl)), sl.seed)
+        torch.cuda.synchronize()
+        out["slice_2^4_copies_vs_oracle_golden"] = hashlib.sha256(ps.proof_bytes()).hexdigest() == gd
+    return out
+
+
 def golden_digest(name):
     p = os.path.join(ROOT, "tests", "golden", "%s_proof.json" % name)
     if not os.path.exists(p):
@@ -394,6 +438,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="leave out the 64-job batched leg")
     ap.add_argument("--no-serving", action="store_true", help="leave out the serving leg")
     ap.add_argument("--no-general", action="store_true", help="leave out the general-circuit leg")
+    ap.add_argument("--no-goldilocks", action="store_true", help="leave out the Goldilocks-field leg")
     ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serving", "copy", "ubench"])
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--jobs", type=int, default=256)
@@ -517,6 +562,13 @@ def main():
         line["general"] = general_leg(gkr, 5, 1, 0 if args.no_profile else 1,
                                       peaks["mad_u64_u32_per_s"] / 1e12 if peaks else None)
         exact["general_vs_oracle_golden"] = line["general"].get("bit_exact_vs_oracle_golden")
+        torch.cuda.empty_cache()
+    if not args.no_goldilocks:
+        log("Goldilocks-field leg")
+        line["goldilocks"] = goldilocks_leg(gkr, 5, 1, 0 if args.no_profile else 1,
+                                            peaks["mad_u64_u32_per_s"] / 1e12 if peaks else None,
+                                            line["ms_per_step"] if args.workload == "c3" else None)
+        exact["goldilocks_slice_vs_oracle_golden"] = line["goldilocks"].get("slice_2^4_copies_vs_oracle_golden")
         torch.cuda.empty_cache()
     if not args.no_batched:
         log("batched leg: 64 uneven jobs")

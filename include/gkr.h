@@ -77,6 +77,11 @@ extern "C" {
 #define GKR_GATE_ADD 0u
 #define GKR_GATE_MUL 1u
 
+/* Fields (Section 4.1, choice of the finite field: BN254, or Goldilocks
+ * p = 2^64 - 2^32 + 1, faster for the prover but without pairings). */
+#define GKR_FIELD_BN254 0u
+#define GKR_FIELD_GOLDILOCKS 1u
+
 /* Largest supported log2 layer width s_i = sigma_i + n, and copy count n. */
 #define GKR_MAX_LOG_WIDTH 30u
 #define GKR_MAX_LOG_COPIES 24u
@@ -144,6 +149,47 @@ const char* gkr_last_error(void);
 int32_t gkr_circuit_create(uint32_t depth, uint32_t log_copies, const uint32_t* log_sub_width,
                            const gkr_gate* const* gates, gkr_circuit** out);
 void gkr_circuit_destroy(gkr_circuit* circuit);
+
+/*
+ * Create a layered circuit over a chosen field (Section 4.1, choice of the
+ * finite field). GKR_FIELD_BN254 is gkr_circuit_create. GKR_FIELD_GOLDILOCKS
+ * gives a circuit proved by gkr_gl_prove_circuit and verified by
+ * gkr_gl_verify over p = 2^64 - 2^32 + 1, with canonical uint64_t elements
+ * (8 bytes; the same wiring, circuit digest and protocol steps) and the
+ * transcript rules of that field:
+ *   init           st = SHA256("SISU-GKR-GL-v1" || LE64(seed))
+ *   accept         v = LE64(st[0..7]); while v >= p: st = SHA256(st || "GKRC"), recompute;
+ *                  the challenge is v
+ *   squeeze        st = SHA256(st || "GKRC"), then accept
+ *   round(e0, e2)  st = C(st, LE64(e0) || LE64(e2) || 47 zero bytes || 0x01), then accept
+ *   values         vx, vy absorbed with "GKRV" as 8 bytes; statement as for BN254 with
+ *                  8-byte elements in the tree digests.
+ * Proof layout as for BN254 with 8-byte elements: (6 s_{i+1} + 2) * 8 bytes
+ * per layer. gkr_workspace_bytes and gkr_proof_bytes report the Goldilocks
+ * sizes; the BN254 proving calls and gkr_verify refuse such a circuit.
+ * Errors: as gkr_circuit_create, and GKR_EINVAL for an unknown field.
+ */
+int32_t gkr_circuit_create_field(uint32_t field, uint32_t depth, uint32_t log_copies,
+                                 const uint32_t* log_sub_width, const gkr_gate* const* gates,
+                                 gkr_circuit** out);
+
+/*
+ * Whole proof of a Goldilocks circuit (Section 2.2 as for gkr_prove_circuit):
+ * d_inputs 2^{s_d} canonical uint64_t (< p), d_outputs receives 2^{s_0}
+ * elements, d_proof gkr_proof_bytes() bytes (device, 8-byte aligned). The
+ * workspace, stream and error conventions are gkr_prove_circuit's.
+ */
+int32_t gkr_gl_prove_circuit(const gkr_circuit* circuit, const uint64_t* d_inputs, uint64_t seed,
+                             uint64_t* d_outputs, uint8_t* d_proof, size_t proof_cap, size_t* proof_len,
+                             void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * Verifier of a Goldilocks proof (Section 2.2 and the round check of Section
+ * 3.2.1, as gkr_verify): host buffers, synchronous; 1 accept, 0 reject,
+ * GKR_EINVAL for a proof of the wrong length or a non-canonical element.
+ */
+int32_t gkr_gl_verify(const gkr_circuit* circuit, const uint64_t* inputs, const uint64_t* outputs,
+                      uint64_t seed, const uint8_t* proof, size_t proof_len);
 
 /*
  * Create a general circuit (Sections 2.7 and 3.4.3, see gkr_nested_gate):

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "gkr_general.hpp"
+#include "gkr_gl.hpp"
 #include "gkr_kernels.hpp"
 #include "gkr_program.hpp"
 #include "gkr_tuning.hpp"
@@ -403,7 +404,8 @@ void Program::state_import(DevState* S, const uint8_t* in) {
 
 void Program::run(hipStream_t s) const {
   for (const Step& st : steps) {
-    if (st.type >= ST_G_GATHER) launch_general_step(st, s);
+    if (st.type >= ST_GL_FORWARD) launch_gl_step(st, s);
+    else if (st.type >= ST_G_GATHER) launch_general_step(st, s);
     else launch_step(st, s);
   }
 }
@@ -517,6 +519,7 @@ static void emit_output_claim(Program& pg, const gkr_circuit& c, const Workspace
 
 static size_t layer_proof_words(const gkr_circuit& c, uint32_t i) {
   if (c.general) return general_layer_proof_bytes(c, i) / 4;
+  if (c.field == GKR_FIELD_GOLDILOCKS) return (6ull * c.s(i + 1) + 2) * 2;
   return (6ull * c.s(i + 1) + 2) * 8;
 }
 
@@ -557,6 +560,15 @@ static int32_t check_launch() {
   if (e != hipSuccess) {
     set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
     return GKR_EDEVICE;
+  }
+  return GKR_OK;
+}
+
+// The BN254 proving calls refuse Goldilocks circuits.
+static int32_t check_bn254(const gkr_circuit* c) {
+  if (c && c->field != GKR_FIELD_BN254) {
+    set_error("this circuit is over the Goldilocks field: use gkr_gl_prove_circuit / gkr_gl_verify");
+    return GKR_EINVAL;
   }
   return GKR_OK;
 }
@@ -747,6 +759,19 @@ int32_t gkr_circuit_create(uint32_t depth, uint32_t log_copies, const uint32_t* 
 
 void gkr_circuit_destroy(gkr_circuit* c) { delete c; }
 
+int32_t gkr_circuit_create_field(uint32_t field, uint32_t depth, uint32_t log_copies, const uint32_t* log_sub_width,
+                                 const gkr_gate* const* gates, gkr_circuit** out) {
+  if (field != GKR_FIELD_BN254 && field != GKR_FIELD_GOLDILOCKS) {
+    set_error("unknown field " + std::to_string(field));
+    return GKR_EINVAL;
+  }
+  const int32_t rc = gkr_circuit_create(depth, log_copies, log_sub_width, gates, out);
+  if (rc != GKR_OK || field == GKR_FIELD_BN254) return rc;
+  (*out)->field = GKR_FIELD_GOLDILOCKS;
+  plan_gl_workspace(**out);
+  return GKR_OK;
+}
+
 size_t gkr_workspace_bytes(const gkr_circuit* c) { return c ? c->plan.total : 0; }
 
 size_t gkr_layer_proof_bytes(const gkr_circuit* c, uint32_t layer) {
@@ -757,6 +782,7 @@ size_t gkr_layer_proof_bytes(const gkr_circuit* c, uint32_t layer) {
 size_t gkr_proof_bytes(const gkr_circuit* c) {
   if (!c) return 0;
   if (c->general) return general_proof_bytes(*c);
+  if (c->field == GKR_FIELD_GOLDILOCKS) return gl_proof_bytes(*c);
   size_t t = 0;
   for (uint32_t i = 0; i < c->depth; ++i) t += layer_proof_words(*c, i) * 4;
   return t;
@@ -772,6 +798,7 @@ uint64_t gkr_gate_layers(const gkr_circuit* c) {
 int32_t gkr_transcript_init(const gkr_circuit* c, uint64_t seed, const gkr_fr* d_inputs,
                             const gkr_fr* d_outputs, gkr_transcript* d_transcript, void* d_ws, size_t ws_bytes,
                             void* stream) {
+  if (int32_t rc = check_bn254(c)) return rc;
   uint8_t* d_state = d_transcript ? d_transcript->state : nullptr;
   if (!c || !d_inputs || !d_outputs || !d_state || !aligned16(d_inputs) || !aligned16(d_outputs)) {
     set_error("null or misaligned argument");
@@ -796,6 +823,7 @@ int32_t gkr_transcript_init(const gkr_circuit* c, uint64_t seed, const gkr_fr* d
 
 int32_t gkr_output_claim(const gkr_circuit* c, const gkr_fr* d_outputs, gkr_transcript* d_transcript,
                          gkr_fr* d_g, gkr_fr* d_claim, void* d_ws, size_t ws_bytes, void* stream) {
+  if (int32_t rc = check_bn254(c)) return rc;
   uint8_t* d_state = d_transcript ? d_transcript->state : nullptr;
   if (!c || !d_outputs || !d_state || !d_claim || (!d_g && c->s(0) > 0) || !aligned16(d_outputs) ||
       (d_g && !aligned16(d_g)) || !aligned16(d_claim)) {
@@ -834,6 +862,7 @@ int32_t gkr_prove_layer(const gkr_circuit* c, uint32_t layer, const gkr_fr* d_ne
     set_error("gkr_prove_layer takes layered circuits only (a general circuit's layers share claims)");
     return GKR_EUNSUPPORTED;
   }
+  if (int32_t rc = check_bn254(c)) return rc;
   const bool first = layer == 0;
   const uint32_t si = c->s(layer), s1 = c->s(layer + 1);
   uint8_t* d_state = d_transcript ? d_transcript->state : nullptr;
@@ -894,6 +923,7 @@ int32_t gkr_prove_circuit(const gkr_circuit* c, const gkr_fr* d_inputs, uint64_t
     set_error("null or misaligned argument");
     return GKR_EINVAL;
   }
+  if (int32_t rc0 = check_bn254(c)) return rc0;
   const size_t need = gkr_proof_bytes(c);
   if (proof_len) *proof_len = need;
   if (proof_cap < need) {

@@ -42,8 +42,8 @@ int32_t gkr_plan_create(const gkr_job* job, gkr_plan** out) {
   }
   *out = nullptr;
   const gkr_circuit* c = job->circuit;
-  if (c->general) {
-    set_error("batch plans take layered circuits only");
+  if (c->general || c->field != GKR_FIELD_BN254) {
+    set_error("batch plans take layered BN254 circuits only");
     return GKR_EUNSUPPORTED;
   }
   if (!job->d_inputs || !job->d_outputs || !job->d_proof || !aligned16b(job->d_inputs) ||

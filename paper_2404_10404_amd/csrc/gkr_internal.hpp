@@ -94,7 +94,20 @@ enum StepType : uint32_t {
   ST_G_P2,
   ST_G_LAYER_BEGIN,
   ST_G_VALUES,
-  ST_G_END
+  ST_G_END,
+  // The Goldilocks-field prover: launched by launch_gl_step, plain path only.
+  ST_GL_FORWARD = 96,
+  ST_GL_DIGEST,
+  ST_GL_BEGIN,
+  ST_GL_SQUEEZE,
+  ST_GL_LAYER_BEGIN,
+  ST_GL_EQ,
+  ST_GL_WSUM,
+  ST_GL_P1,
+  ST_GL_P2,
+  ST_GL_ROUND,
+  ST_GL_TAIL,
+  ST_GL_END
 };
 
 struct Step {
@@ -146,11 +159,30 @@ struct Plan {
 
 namespace gkr {
 struct GeneralInfo;  // general circuits only (gkr_general.hip)
-}
+
+// Scalars of one Goldilocks proof in device memory (canonical 64-bit elements).
+struct GlState {
+  uint32_t st[8];   // transcript chaining value, SHA-256 words h[0..7]
+  uint32_t counter; // last-workgroup counter of grid reductions (returns to 0)
+  uint32_t pad;
+  uint64_t claim, alpha, beta, vx, vy;
+  uint64_t scratch[4];  // [0] the output claim V_0~(g)
+};
+
+// Workspace layout of a Goldilocks proof: layers 1..d-1 (layer d is the
+// caller's inputs, layer 0 the caller's outputs), tables, state.
+struct GlPlan {
+  size_t off_layer[GKR_MAX_DEPTH + 1];
+  size_t off_G, off_H, off_Wf, off_aU, off_bV, off_Cu, off_Cv, off_EL, off_EC, off_partials, off_dig_a,
+      off_dig_b, off_dig_in, off_dig_out, off_chal, off_state;
+};
+}  // namespace gkr
 
 struct gkr_circuit {
   uint32_t depth = 0, n = 0;
   gkr::GeneralInfo* general = nullptr;        // non-null for a general circuit
+  uint32_t field = GKR_FIELD_BN254;           // GKR_FIELD_GOLDILOCKS: proved by gkr_gl_prove_circuit
+  gkr::GlPlan gl;                             // Goldilocks workspace layout
   ~gkr_circuit();                             // frees the device block and the general description
   std::vector<uint32_t> sigma;                // [depth+1]
   std::vector<std::vector<gkr_gate>> gates;   // host copy of each layer's sub-circuit

@@ -18,7 +18,9 @@
 #include <vector>
 
 #include "gkr_general.hpp"
+#include "gkr_gl.hpp"
 #include "gkr_internal.hpp"
+#include "gl.hpp"
 
 namespace gkr {
 namespace {
@@ -343,9 +345,190 @@ int32_t general_verify(const gkr_circuit& c, const gkr_fr* inputs, const gkr_fr*
   return accept ? 1 : 0;
 }
 
+// ---------------------------------------------------------------- Goldilocks
+
+namespace {
+
+std::vector<uint64_t> gl_eq_table_host(const uint64_t* r, uint32_t k) {
+  std::vector<uint64_t> t(1ull << k);
+  t[0] = 1;
+  for (uint32_t i = 0; i < k; ++i) {
+    const uint64_t cur = 1ull << i, ri = r[i], ni = gl_one_minus(r[i]);
+    for (uint64_t b = cur; b-- > 0;) {
+      const uint64_t v = t[b];
+      t[2 * b + 1] = gl_mul(v, ri);
+      t[2 * b] = gl_mul(v, ni);
+    }
+  }
+  return t;
+}
+
+uint64_t gl_mle_host(const uint64_t* V, uint32_t k, const uint64_t* r) {
+  if (k == 0) return V[0];
+  std::vector<uint64_t> cur(V, V + (1ull << k));
+  uint64_t m = 1ull << k;
+  for (uint32_t j = 0; j < k; ++j) {
+    const uint64_t h = m / 2;
+    for (uint64_t b = 0; b < h; ++b) cur[b] = gl_add(cur[b], gl_mul(r[j], gl_sub(cur[b + h], cur[b])));
+    m = h;
+  }
+  return cur[0];
+}
+
+uint64_t gl_triple_eq(const uint64_t* a, const uint64_t* b, const uint64_t* c, uint32_t k) {
+  uint64_t acc = 1;
+  for (uint32_t i = 0; i < k; ++i) {
+    const uint64_t t1 = gl_mul(gl_mul(a[i], b[i]), c[i]);
+    const uint64_t t0 = gl_mul(gl_mul(gl_one_minus(a[i]), gl_one_minus(b[i])), gl_one_minus(c[i]));
+    acc = gl_mul(acc, gl_add(t1, t0));
+  }
+  return acc;
+}
+
+struct GlHostTranscript {
+  HostTranscript t;
+  uint64_t accept() {
+    uint64_t v = (uint64_t)bswap32(t.st.h[0]) | ((uint64_t)bswap32(t.st.h[1]) << 32);
+    while (v >= kGlP) {
+      t.absorb_words(kTagChallenge, nullptr, 0);
+      v = (uint64_t)bswap32(t.st.h[0]) | ((uint64_t)bswap32(t.st.h[1]) << 32);
+    }
+    return v;
+  }
+  uint64_t squeeze() {
+    t.absorb_words(kTagChallenge, nullptr, 0);
+    return accept();
+  }
+  void absorb_value(uint64_t v) {
+    const uint32_t w[2] = {bswap32((uint32_t)v), bswap32((uint32_t)(v >> 32))};
+    t.absorb_words(kTagValue, w, 2);
+  }
+  uint64_t round(uint64_t e0, uint64_t e2) {
+    Sha256Block blk;
+    for (int k = 0; k < 16; ++k) blk.w[k] = 0;
+    blk.w[0] = bswap32((uint32_t)e0);
+    blk.w[1] = bswap32((uint32_t)(e0 >> 32));
+    blk.w[2] = bswap32((uint32_t)e2);
+    blk.w[3] = bswap32((uint32_t)(e2 >> 32));
+    blk.w[15] = 1u;
+    t.st = sha256_compress_v(t.st, blk);
+    return accept();
+  }
+};
+
+}  // namespace
 }  // namespace gkr
 
 using namespace gkr;
+
+extern "C" int32_t gkr_gl_verify(const gkr_circuit* c, const uint64_t* inputs, const uint64_t* outputs,
+                                 uint64_t seed, const uint8_t* proof, size_t proof_len) {
+  try {
+    if (!c || !inputs || !outputs || !proof) {
+      set_error("null argument");
+      return GKR_EINVAL;
+    }
+    if (c->field != GKR_FIELD_GOLDILOCKS) {
+      set_error("gkr_gl_verify takes circuits created for the Goldilocks field");
+      return GKR_EINVAL;
+    }
+    const uint32_t d = c->depth, n = c->n;
+    const size_t need = gl_proof_bytes(*c);
+    if (proof_len != need) {
+      set_error("proof length " + std::to_string(proof_len) + ", expected " + std::to_string(need));
+      return GKR_EINVAL;
+    }
+    const uint64_t nin = 1ull << c->s(d), nout = 1ull << c->s(0);
+    const uint64_t* pf = reinterpret_cast<const uint64_t*>(proof);
+    for (uint64_t i = 0; i < nin; ++i)
+      if (inputs[i] >= kGlP) { set_error("element not canonical"); return GKR_EINVAL; }
+    for (uint64_t i = 0; i < nout; ++i)
+      if (outputs[i] >= kGlP) { set_error("element not canonical"); return GKR_EINVAL; }
+    for (uint64_t i = 0; i < need / 8; ++i) {
+      uint64_t v;
+      memcpy(&v, proof + 8 * i, 8);
+      if (v >= kGlP) { set_error("element not canonical"); return GKR_EINVAL; }
+    }
+    std::vector<uint64_t> pv(need / 8);
+    memcpy(pv.data(), pf, need);
+    uint64_t pos = 0;
+    GlHostTranscript tr;
+    {
+      uint8_t msg[22];
+      memcpy(msg, "SISU-GKR-GL-v1", 14);
+      for (int k = 0; k < 8; ++k) msg[14 + k] = (uint8_t)(seed >> (8 * k));
+      sha256_bytes(msg, sizeof(msg), tr.t.st.h);
+    }
+    uint32_t dig[8];
+    tr.t.absorb_words(kTagDigest, c->digest, 8);
+    tree_digest_host(reinterpret_cast<const uint8_t*>(inputs), nin * 8, dig);
+    tr.t.absorb_words(kTagDigest, dig, 8);
+    tree_digest_host(reinterpret_cast<const uint8_t*>(outputs), nout * 8, dig);
+    tr.t.absorb_words(kTagDigest, dig, 8);
+    std::vector<uint64_t> u(c->s(0)), v;
+    for (auto& x : u) x = tr.squeeze();
+    uint64_t vu = gl_mle_host(outputs, c->s(0), u.data()), vv = 0;
+    bool accept = true;
+    for (uint32_t i = 0; i < d; ++i) {
+      uint64_t alpha = 1, beta = 0;
+      if (i > 0) {
+        alpha = tr.squeeze();
+        beta = tr.squeeze();
+      }
+      uint64_t claim = gl_add(gl_mul(alpha, vu), gl_mul(beta, vv));
+      const uint32_t s1 = c->s(i + 1), sg = c->sigma[i], sg1 = c->sigma[i + 1];
+      std::vector<uint64_t> rxy[2];
+      uint64_t vals[2];
+      for (int ph = 0; ph < 2; ++ph) {
+        for (uint32_t j = 0; j < s1; ++j) {
+          const uint64_t e0 = pv[pos], e1 = pv[pos + 1], e2 = pv[pos + 2];
+          pos += 3;
+          if (gl_add(e0, e1) != claim) accept = false;
+          const uint64_t r = tr.round(e0, e2);
+          rxy[ph].push_back(r);
+          claim = gl_interp3(e0, e1, e2, r);
+        }
+        vals[ph] = pv[pos++];
+        tr.absorb_value(vals[ph]);
+      }
+      const std::vector<uint64_t>& rx = rxy[0];
+      const std::vector<uint64_t>& ry = rxy[1];
+      const std::vector<uint64_t> elx = gl_eq_table_host(rx.data(), sg1), ely = gl_eq_table_host(ry.data(), sg1);
+      const std::vector<uint64_t> wu = gl_eq_table_host(u.data(), sg);
+      const uint64_t cu = gl_triple_eq(u.data() + sg, rx.data() + sg1, ry.data() + sg1, n);
+      std::vector<uint64_t> wv;
+      uint64_t cv = 0;
+      if (i > 0) {
+        wv = gl_eq_table_host(v.data(), sg);
+        cv = gl_triple_eq(v.data() + sg, rx.data() + sg1, ry.data() + sg1, n);
+      }
+      uint64_t add_v = 0, mul_v = 0;
+      const std::vector<gkr_gate>& gl_ = c->gates[i];
+      for (size_t z = 0; z < gl_.size(); ++z) {
+        uint64_t wgt = gl_mul(gl_mul(alpha, wu[z]), cu);
+        if (i > 0) wgt = gl_add(wgt, gl_mul(gl_mul(beta, wv[z]), cv));
+        const uint64_t term = gl_mul(gl_mul(wgt, elx[gl_[z].x]), ely[gl_[z].y]);
+        if (gl_[z].type == GKR_GATE_MUL) mul_v = gl_add(mul_v, term);
+        else add_v = gl_add(add_v, term);
+      }
+      const uint64_t vx = vals[0], vy = vals[1];
+      const uint64_t fin = gl_add(gl_mul(gl_mul(mul_v, vx), vy), gl_mul(add_v, gl_add(vx, vy)));
+      if (fin != claim) accept = false;
+      u = rx;
+      v = ry;
+      vu = vx;
+      vv = vy;
+    }
+    if (accept) {
+      if (vu != gl_mle_host(inputs, c->s(d), u.data())) accept = false;
+      if (accept && vv != gl_mle_host(inputs, c->s(d), v.data())) accept = false;
+    }
+    return accept ? 1 : 0;
+  } catch (...) {
+    set_error("verifier failure (allocation)");
+    return GKR_ENOMEM;
+  }
+}
 
 extern "C" int32_t gkr_verify(const gkr_circuit* c, const gkr_fr* inputs, const gkr_fr* outputs,
                               uint64_t seed, const uint8_t* proof, size_t proof_len) {
@@ -355,6 +538,10 @@ extern "C" int32_t gkr_verify(const gkr_circuit* c, const gkr_fr* inputs, const 
       return GKR_EINVAL;
     }
     if (c->general) return general_verify(*c, inputs, outputs, seed, proof, proof_len);
+    if (c->field != GKR_FIELD_BN254) {
+      set_error("this circuit is over the Goldilocks field: use gkr_gl_verify");
+      return GKR_EINVAL;
+    }
     const uint32_t d = c->depth, n = c->n;
     size_t need = 0;
     for (uint32_t i = 0; i < d; ++i) need += (6ull * c->s(i + 1) + 2) * 32;

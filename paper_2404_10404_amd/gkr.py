@@ -30,8 +30,13 @@ EXPORTS = (
     "gkr_transcript_init", "gkr_output_claim", "gkr_prove_layer", "gkr_verify",
     "gkr_plan_create", "gkr_plan_destroy", "gkr_plan_reset", "gkr_run_batch", "gkr_plan_progress",
     "gkr_prove_batch", "gkr_set_tuning", "gkr_get_tuning", "gkr_profile_enable", "gkr_profile_read",
-    "gkr_ubench", "gkr_prove_circuit_noalloc", "gkr_general_circuit_create",
+    "gkr_ubench", "gkr_prove_circuit_noalloc", "gkr_general_circuit_create", "gkr_circuit_create_field",
+    "gkr_gl_prove_circuit", "gkr_gl_verify",
 )
+
+FIELD_BN254 = 0
+FIELD_GOLDILOCKS = 1
+GOLDILOCKS_P = (1 << 64) - (1 << 32) + 1
 
 # Size of the static workspace of gkr_prove_circuit_noalloc (GKR_NOALLOC_WORKSPACE_BYTES).
 NOALLOC_WORKSPACE_BYTES = 256 << 20
@@ -81,6 +86,13 @@ def lib() -> ctypes.CDLL:
         L.gkr_general_circuit_create.argtypes = [_u32, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_u64),
                                                  ctypes.POINTER(ctypes.POINTER(NestedGate)), ctypes.POINTER(_vp)]
         L.gkr_general_circuit_create.restype = _i32
+        L.gkr_circuit_create_field.argtypes = [_u32, _u32, _u32, ctypes.POINTER(_u32),
+                                               ctypes.POINTER(ctypes.POINTER(Gate)), ctypes.POINTER(_vp)]
+        L.gkr_circuit_create_field.restype = _i32
+        L.gkr_gl_prove_circuit.argtypes = [_vp, _vp, _u64, _vp, _vp, _sz, ctypes.POINTER(_sz), _vp, _sz, _vp]
+        L.gkr_gl_prove_circuit.restype = _i32
+        L.gkr_gl_verify.argtypes = [_vp, _vp, _vp, _u64, _vp, _sz]
+        L.gkr_gl_verify.restype = _i32
         L.gkr_circuit_destroy.argtypes = [_vp]
         L.gkr_circuit_destroy.restype = None
         for name in ("gkr_workspace_bytes", "gkr_proof_bytes"):
@@ -154,10 +166,11 @@ def _elements(arr) -> np.ndarray:
 
 
 class Circuit:
-    """A circuit object of the library (wiring uploaded to the current device)."""
+    """A circuit object of the library (wiring uploaded to the current device).
+    field: FIELD_BN254 (gkr_circuit_create) or FIELD_GOLDILOCKS."""
 
     def __init__(self, depth: int, log_copies: int, log_sub_width: Sequence[int],
-                 wiring: Sequence[Tuple[np.ndarray, np.ndarray, np.ndarray]]):
+                 wiring: Sequence[Tuple[np.ndarray, np.ndarray, np.ndarray]], field: int = FIELD_BN254):
         L = lib()
         self.depth, self.log_copies = int(depth), int(log_copies)
         self.log_sub_width = [int(s) for s in log_sub_width]
@@ -170,13 +183,17 @@ class Circuit:
             self._gate_arrays.append(g)
             ptrs[i] = g.ctypes.data_as(ctypes.POINTER(Gate))
         h = _vp()
-        _check(L.gkr_circuit_create(self.depth, self.log_copies, sig, ptrs, ctypes.byref(h)))
+        self.field = int(field)
+        if self.field == FIELD_BN254:
+            _check(L.gkr_circuit_create(self.depth, self.log_copies, sig, ptrs, ctypes.byref(h)))
+        else:
+            _check(L.gkr_circuit_create_field(self.field, self.depth, self.log_copies, sig, ptrs, ctypes.byref(h)))
         self._h = h
         self._gate_arrays = None
 
     @classmethod
-    def from_synth(cls, spec, wiring) -> "Circuit":
-        return cls(spec.depth, spec.log_copies, spec.log_sub_width, [(w.x, w.y, w.kind) for w in wiring])
+    def from_synth(cls, spec, wiring, field: int = FIELD_BN254) -> "Circuit":
+        return cls(spec.depth, spec.log_copies, spec.log_sub_width, [(w.x, w.y, w.kind) for w in wiring], field)
 
     @property
     def handle(self):
@@ -286,6 +303,51 @@ def prove_circuit_noalloc(c: Circuit, d_inputs, seed: int, d_outputs, d_proof, s
                                            _ptr(d_proof), d_proof.numel() * d_proof.element_size(),
                                            ctypes.byref(plen), _stream(stream)))
     return plen.value
+
+
+def gl_device_elements(arr, device="cuda"):
+    """Upload canonical Goldilocks elements (uint64) as a torch int64 tensor."""
+    import torch
+    a = np.ascontiguousarray(arr, dtype=np.uint64)
+    return torch.from_numpy(a.view(np.int64)).to(device)
+
+
+def gl_prove_circuit(c: Circuit, d_inputs, seed: int, d_outputs, d_proof, d_ws, stream=None) -> int:
+    """gkr_gl_prove_circuit on caller tensors (int64 views of the elements)."""
+    plen = _sz(0)
+    _check(lib().gkr_gl_prove_circuit(c.handle, _ptr(d_inputs), seed & (2**64 - 1), _ptr(d_outputs),
+                                      _ptr(d_proof), d_proof.numel() * d_proof.element_size(), ctypes.byref(plen),
+                                      _ptr(d_ws), d_ws.numel() * d_ws.element_size(), _stream(stream)))
+    return plen.value
+
+
+def gl_verify(c: Circuit, inputs, outputs, seed: int, proof: bytes) -> int:
+    """gkr_gl_verify on host buffers (uint64 elements)."""
+    a = np.ascontiguousarray(inputs, dtype=np.uint64)
+    b = np.ascontiguousarray(outputs, dtype=np.uint64)
+    pb = np.frombuffer(bytes(proof), dtype=np.uint8)
+    return _check(lib().gkr_gl_verify(c.handle, a.ctypes.data, b.ctypes.data, seed & (2**64 - 1),
+                                      pb.ctypes.data if pb.size else None, pb.size))
+
+
+class GlProver:
+    """Device buffers of one Goldilocks proof at a time for one circuit."""
+
+    def __init__(self, c: Circuit, device="cuda"):
+        import torch
+        self.c = c
+        self.ws = alloc_bytes(c.workspace_bytes, device)
+        self.proof = alloc_bytes(c.proof_bytes, device)
+        self.outputs = torch.empty(1 << c.s(0), dtype=torch.int64, device=device)
+
+    def prove(self, d_inputs, seed: int, stream=None) -> int:
+        return gl_prove_circuit(self.c, d_inputs, seed, self.outputs, self.proof, self.ws, stream)
+
+    def proof_bytes(self) -> bytes:
+        return bytes(self.proof[: self.c.proof_bytes].cpu().numpy().tobytes())
+
+    def host_outputs(self) -> np.ndarray:
+        return self.outputs.cpu().numpy().view(np.uint64)
 
 
 def transcript_init(c: Circuit, seed: int, d_inputs, d_outputs, d_state, d_ws, stream=None):

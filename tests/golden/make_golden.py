@@ -9,7 +9,8 @@ workload, the SHA-256 of the outputs and of the proof, and the proof itself
 
 "g1" is the general-circuit workload (accumulation gates, right inputs from
 up to four layers back, oracle/general.py); "g1slice" the same sub-circuit
-with 2^2 copies.
+with 2^2 copies. "gl_c3slice" and "gl_c2" are the Goldilocks variant
+(oracle/goldilocks.py) of the c3 slice and of c2.
 """
 import hashlib
 import json
@@ -26,6 +27,7 @@ import dataclasses  # noqa: E402
 import gkr_synth as gs  # noqa: E402
 from oracle import circuit as oc  # noqa: E402
 from oracle import general as og  # noqa: E402
+from oracle import goldilocks as ogl  # noqa: E402
 from oracle import prover as op  # noqa: E402
 from oracle.field import encode_all  # noqa: E402
 
@@ -67,9 +69,39 @@ def make_general(name):
     print(name, "done in %.1f s" % (time.time() - t0), flush=True)
 
 
+# the Goldilocks variant (oracle/goldilocks.py) of the layered workloads
+GOLDILOCKS_CASES = {
+    "gl_c3slice": lambda: gs.copy_slice(gs.worker_share_c3(), 4),
+    "gl_c2": gs.data_parallel_c2,
+}
+
+
+def make_goldilocks(name):
+    spec = GOLDILOCKS_CASES[name]()
+    t0 = time.time()
+    wiring = gs.make_wiring(spec)
+    inputs = [int(v) for v in gs.make_goldilocks_inputs(spec)]
+    pt = ogl.prove(oc.Circuit.from_synth(spec, wiring), inputs, spec.seed)
+    proof = pt.proof_bytes()
+    rec = {
+        "workload": name, "field": "goldilocks", "depth": spec.depth, "log_copies": spec.log_copies,
+        "log_sub_width": list(spec.log_sub_width), "mu": list(spec.mu), "seed": spec.seed,
+        "outputs_sha256": hashlib.sha256(ogl.encode_all(pt.outputs)).hexdigest(),
+        "proof_sha256": hashlib.sha256(proof).hexdigest(),
+        "proof_len": len(proof),
+        "oracle_seconds": round(time.time() - t0, 1),
+        "writer": "tests/golden/make_golden.py (CPU oracle)",
+    }
+    with open(os.path.join(HERE, "%s_proof.json" % name), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(name, "done in %.1f s" % (time.time() - t0), flush=True)
+
+
 def make(name):
     if name in GENERAL_CASES:
         return make_general(name)
+    if name in GOLDILOCKS_CASES:
+        return make_goldilocks(name)
     spec = CASES[name][0]()
     t0 = time.time()
     wiring = gs.make_wiring(spec)

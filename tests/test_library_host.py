@@ -192,3 +192,27 @@ def test_general_circuit_validation():
 
 def test_abi_struct_sizes():
     assert ctypes.sizeof(gkr.Gate) == 12 and ctypes.sizeof(gkr.NestedGate) == 20
+
+
+@pytest.mark.parametrize("shape", [(3, 2, (3, 4, 2, 3), 11), (4, 0, (5, 5, 5, 5, 5), 12), (1, 0, (0, 0), 13),
+                                   (2, 4, (6, 6, 6), 14)])
+def test_host_goldilocks_verifier_accepts_oracle_proofs(shape):
+    """The Goldilocks circuit object (proof length, digest) and host verifier
+    agree with the Goldilocks oracle; the BN254 calls refuse the circuit."""
+    from oracle import goldilocks as ogl
+    depth, n, sig, seed = shape
+    spec = gs.CircuitSpec(depth=depth, log_copies=n, log_sub_width=tuple(sig), seed=seed)
+    wiring = gs.make_wiring(spec)
+    inputs = gs.make_goldilocks_inputs(spec)
+    pt = ogl.prove(oc.Circuit.from_synth(spec, wiring), [int(v) for v in inputs], seed)
+    c = gkr.Circuit.from_synth(spec, wiring, field=gkr.FIELD_GOLDILOCKS)
+    proof = pt.proof_bytes()
+    assert c.proof_bytes == len(proof) == ogl.proof_length(oc.Circuit.from_synth(spec, wiring))
+    outs = np.array(pt.outputs, dtype=np.uint64)
+    assert gkr.gl_verify(c, inputs, outs, seed, proof) == 1
+    for k in range(0, len(proof) // 8, 2):
+        bad = bytearray(proof)
+        bad[8 * k] ^= 1
+        assert gkr.gl_verify(c, inputs, outs, seed, bytes(bad)) in (0, gkr.GKR_EINVAL), k
+    with pytest.raises(gkr.GkrError):
+        gkr.verify(c, gs.make_inputs(spec), gs.make_inputs(spec)[:1 << c.s(0)], seed, proof)
