@@ -99,24 +99,28 @@ CLASS_KERNEL = {"round": "k_round_a", "round_sub": "k_round_b", "tail": "k_tail_
                 "g_forward": "k_g_forward", "g_claim_tables": "k_g_ttable", "g_phase1_init": "k_g_p1",
                 "g_phase2_tables": "k_g_p2"}
 KERNEL_SOURCES = ["fr.hpp", "sha256.hpp", "gkr_device.hpp", "gkr_kernels.hpp", "gkr_bodies.hpp", "gkr_kernels.hip"]
+# The Goldilocks prover's classes and the sources its kernels are built from.
+GL_CLASS_KERNEL = {"round": "k_gl_round", "tail": "k_gl_tail", "phase1_init": "k_gl_p1",
+                   "phase2_tables": "k_gl_p2", "forward": "k_gl_forward", "digest": "k_gl_digest"}
+GL_KERNEL_SOURCES = ["fr.hpp", "sha256.hpp", "gkr_device.hpp", "gkr_kernels.hpp", "gkr_bodies.hpp", "gl.hpp", "gkr_gl.hip"]
 
 
-def kernel_sources_digest():
+def kernel_sources_digest(sources=None):
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2404_10404_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def traffic_record(kernel, workload):
+def traffic_record(kernel, workload, sources=None):
     """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE, WRITE_SIZE runs,
     scaled by a plain copy of known size), from the summaries under profiles/;
     None when no record exists or the kernel sources changed since."""
     d = os.path.join(ROOT, "profiles")
     if not os.path.isdir(d):
         return None
-    digest = kernel_sources_digest()
+    digest = kernel_sources_digest(sources)
     for name in sorted(os.listdir(d)):
         if not name.endswith(".md"):
             continue
@@ -131,7 +135,8 @@ def traffic_record(kernel, workload):
     return None
 
 
-def roofline(prof, workload=None, mac_peak_tops=None, macs_per_mulmod=MACS_PER_MULMOD):
+def roofline(prof, workload=None, mac_peak_tops=None, macs_per_mulmod=MACS_PER_MULMOD, class_kernel=None,
+             sources=None):
     """Roofline of the dominant kernel class: t_roof = max(bytes / HBM peak,
     multiply-adds / integer-multiply peak); the bound is the larger term.
     The integer peak is the measured v_mad_u64_u32 rate when given; a field
@@ -158,8 +163,8 @@ def roofline(prof, workload=None, mac_peak_tops=None, macs_per_mulmod=MACS_PER_M
               "avg_launch_us": round(e["ms"] * 1e3 / max(1, e["launches"]), 2),
               "hbm_gbs": round(gbs, 1), "alu_tops": round(tops, 3),
               "algorithmic_bytes_per_launch": round(e["bytes"] / max(1, e["launches"]))})
-    kern = CLASS_KERNEL.get(name)
-    t = traffic_record(kern, workload) if kern and workload else None
+    kern = (class_kernel or CLASS_KERNEL).get(name)
+    t = traffic_record(kern, workload, sources) if kern and workload else None
     r["traffic"] = None if t is None else round(t)
     return r
 
@@ -385,7 +390,8 @@ def goldilocks_leg(gkr, steps, warmup, profile_steps, mac_peak_tops, bn254_ms=No
         out["speedup_vs_bn254"] = round(bn254_ms / (dt * 1e3), 2)
     if profile_steps:
         prof = profile_pass(gkr, prover, d_in, spec.seed, profile_steps)
-        out["roofline"] = roofline(prof, "gl_c3", mac_peak_tops, macs_per_mulmod=4)
+        out["roofline"] = roofline(prof, "gl_c3", mac_peak_tops, macs_per_mulmod=4, class_kernel=GL_CLASS_KERNEL,
+                                   sources=GL_KERNEL_SOURCES)
         out["kernels"] = {k: {"ms": round(v["ms"], 4), "launches": v["launches"]} for k, v in
                           sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:8]}
     del prover, d_in
