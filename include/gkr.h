@@ -418,6 +418,83 @@ int32_t gkr_profile_read(gkr_profile_entry* out, uint32_t cap, uint32_t* count);
  */
 int32_t gkr_ubench(uint32_t kind, uint32_t iters, double* ops_per_s, double* ms);
 
+/*
+ * Committed inputs (Section 2.4, the Virgo protocol: the prover commits to
+ * the input layer's multilinear extension before the GKR protocol runs and
+ * opens it at the last layer's two points, so the verifier never reads the
+ * inputs; the commitment is transparent and built on a univariate sumcheck).
+ * This library's construction, for N = 2^s inputs V:
+ *   - f(X) = sum_b V[b] X^b; f is evaluated on the coset L = 5 <w_M>, M = 4N
+ *     (w_M = 5^((p-1)/M); so s <= 26), and a table over a coset is stored in
+ *     bit-reversed order: position t holds the value at 5 w_M^bitrev(t).
+ *   - Merkle trees: leaf u covers positions 2u, 2u + 1 of a table (64 bytes:
+ *     the Montgomery forms e 2^256 mod p, 32 bytes little-endian each) or of
+ *     two tables (128 bytes, h then g'); a leaf digest is the SHA-256
+ *     compression function chained from the initial hash value over its
+ *     64-byte blocks (no padding), a node the compression of left || right.
+ *   - The statement absorbs ("GKRD", root of f) in place of the input
+ *     digest. After the last layer, with points rx, ry and claims vx, vy:
+ *     lam = squeeze, c = vx + lam vy = sum_b V[b] w[b], w = eq(rx, .) +
+ *     lam eq(ry, .); q(X) = sum_b w[b] X^((N - b) mod N) (the verifier
+ *     evaluates it in O(s): q(x) = x^N Q(1/x) + (1 - x^N) Q(0), Q(Y) =
+ *     prod_j ((1 - rx_j) + rx_j Y^(2^(s-j))) + lam prod_j (same with ry));
+ *     the prover splits f q = c + X g' + (X^N - 1) h (deg g', h < N - 1),
+ *     absorbs ("GKRM", root of (h, g')), squeezes a0..a3, and runs FRI on
+ *     R = a0 f + a1 h + a2 g' + a3 X g' (degree < N): for i < s, beta_i =
+ *     squeeze, fold R_{i+1}(x^2) = (R_i(x) + R_i(-x)) / 2 + beta_i (R_i(x) -
+ *     R_i(-x)) / (2x), and for i + 1 < s absorb ("GKRM", root of R_{i+1});
+ *     the constant R_s is absorbed with "GKRV"; then `queries` leaves u_j =
+ *     squeeze mod (M / 2) of the first layer.
+ *   - Proof: root of f || the layered proof (layout above) || root of (h, g')
+ *     || roots of R_1..R_{s-1} || R_s || per query: f leaf (2 elements) and
+ *     its path (s + 1 digests), (h, g') leaf (4 elements) and path, and for
+ *     i = 1..s-1 the leaf u_j >> i of R_i (2 elements) and its path (s + 1 - i
+ *     digests); paths bottom-up, elements canonical, digests as SHA-256 bytes.
+ *
+ * gkr_committed_sizes: workspace and proof bytes of a committed proof of a
+ * layered BN254 circuit with depth >= 1 and 2^1 .. 2^26 inputs, for 1 ..
+ * GKR_MAX_QUERIES queries (either output may be NULL). Errors:
+ * GKR_EUNSUPPORTED (general or Goldilocks circuit, input count out of range),
+ * GKR_EINVAL.
+ */
+#define GKR_MAX_QUERIES 256u
+int32_t gkr_committed_sizes(const gkr_circuit* circuit, uint32_t queries, size_t* ws_bytes,
+                            size_t* proof_bytes);
+
+/*
+ * The committed-input proof of outputs = C(inputs) (Section 2.4 with the
+ * layered proof of gkr_prove_circuit between commitment and opening).
+ * d_inputs, d_outputs, d_proof, d_ws as for gkr_prove_circuit (16-byte
+ * aligned device buffers; the workspace of gkr_committed_sizes, 16-byte
+ * aligned); proof_cap >= the proof bytes. Queued on `stream`; allocates
+ * nothing. Errors: GKR_EINVAL, GKR_EBUFSZ, GKR_EUNSUPPORTED, GKR_EDEVICE.
+ */
+int32_t gkr_prove_circuit_committed(const gkr_circuit* circuit, const gkr_fr* d_inputs, uint64_t seed,
+                                    uint32_t queries, gkr_fr* d_outputs, uint8_t* d_proof, size_t proof_cap,
+                                    void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * Verifier of a committed-input proof (the GKR round and layer checks of
+ * gkr_verify, then the opening: Merkle paths, the identity
+ * f(x) q(x) = c + x g'(x) + (x^N - 1) h(x) at each queried x and -x, and the
+ * FRI folds down to R_s). It reads the outputs but not the inputs: host
+ * buffers, synchronous; 1 accept, 0 reject, GKR_EINVAL for a proof of the
+ * wrong length or a non-canonical element in the layered part.
+ */
+int32_t gkr_verify_committed(const gkr_circuit* circuit, const gkr_fr* outputs, uint64_t seed, uint32_t queries,
+                             const uint8_t* proof, size_t proof_len);
+
+/*
+ * The commitment alone (Section 2.4's commit step) to 2^log_n canonical
+ * values d_values (device, 1 <= log_n <= 26): writes the 32-byte root to
+ * d_root (device). gkr_vpd_workspace_bytes gives the workspace size (device,
+ * 16-byte aligned). Queued on `stream`; allocates nothing. Errors:
+ * GKR_EUNSUPPORTED, GKR_EINVAL, GKR_EBUFSZ, GKR_EDEVICE.
+ */
+int32_t gkr_vpd_workspace_bytes(uint32_t log_n, size_t* bytes);
+int32_t gkr_vpd_commit(uint32_t log_n, const gkr_fr* d_values, uint8_t* d_root, void* d_ws, size_t ws_bytes,
+                       void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,6 +15,7 @@
  * the pure-Python oracle would take minutes.
  */
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 typedef unsigned __int128 u128;
@@ -178,4 +179,39 @@ void oracle_mle(const uint64_t* values, uint32_t k, const uint64_t* r, uint64_t*
     half >>= 1;
   }
   memcpy(out, scratch, 32);
+}
+
+/*
+ * f(x) = sum_b c[b] x^b for `count` canonical coefficients c (the committed
+ * polynomial of the input-layer commitment), x canonical: Horner's rule over
+ * blocks of 2^16 coefficients, the block values combined by powers of x.
+ */
+void oracle_poly_eval(const uint64_t* coeffs, uint64_t count, const uint64_t* x, uint64_t* out) {
+  init();
+  const uint64_t B = 1ULL << 16;
+  const uint64_t nblocks = (count + B - 1) / B;
+  uint64_t* part = (uint64_t*)calloc(nblocks * 4 ? nblocks * 4 : 4, sizeof(uint64_t));
+#pragma omp parallel for schedule(static) if (nblocks > 1)
+  for (uint64_t blk = 0; blk < nblocks; ++blk) {
+    uint64_t acc[4] = {0, 0, 0, 0}, t[4];
+    const uint64_t lo = blk * B, hi = (lo + B < count) ? lo + B : count;
+    for (uint64_t i = hi; i-- > lo;) {
+      mulmod(acc, x, t);
+      addmod(t, coeffs + 4 * i, acc);
+    }
+    memcpy(part + 4 * blk, acc, 32);
+  }
+  /* x^B, then sum_blk part[blk] (x^B)^blk by Horner over the blocks */
+  uint64_t xb[4], t[4], acc[4] = {0, 0, 0, 0};
+  memcpy(xb, x, 32);
+  for (int k = 0; k < 16; ++k) {
+    mulmod(xb, xb, t);
+    memcpy(xb, t, 32);
+  }
+  for (uint64_t blk = nblocks; blk-- > 0;) {
+    mulmod(acc, xb, t);
+    addmod(t, part + 4 * blk, acc);
+  }
+  memcpy(out, acc, 32);
+  free(part);
 }

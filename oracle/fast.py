@@ -36,6 +36,7 @@ def lib():
         L.oracle_mulmod_many.argtypes = [vp, vp, vp, ctypes.c_uint64]
         L.oracle_addsub_many.argtypes = [vp, vp, vp, vp, ctypes.c_uint64]
         L.oracle_mle.argtypes = [vp, ctypes.c_uint32, vp, vp, vp]
+        L.oracle_poly_eval.argtypes = [vp, ctypes.c_uint64, vp, vp]
         _lib = L
     return _lib
 
@@ -81,4 +82,13 @@ def mle_limbs(limbs: np.ndarray, r) -> int:
     scratch = np.zeros((max(1, V.shape[0] // 2), 4), dtype=np.uint64)
     out = np.zeros((1, 4), dtype=np.uint64)
     lib().oracle_mle(V.ctypes.data, k, R.ctypes.data, scratch.ctypes.data, out.ctypes.data)
+    return _words_to_ints(out)[0]
+
+
+def poly_eval_limbs(limbs: np.ndarray, x: int) -> int:
+    """f(x) = sum_b V[b] x^b for V given as canonical (count, 8) uint32 limbs."""
+    V = _words(limbs)
+    X = _ints_to_words([x])
+    out = np.zeros((1, 4), dtype=np.uint64)
+    lib().oracle_poly_eval(V.ctypes.data, V.shape[0], X.ctypes.data, out.ctypes.data)
     return _words_to_ints(out)[0]

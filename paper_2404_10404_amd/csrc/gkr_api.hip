@@ -13,6 +13,7 @@
 #include "gkr_kernels.hpp"
 #include "gkr_program.hpp"
 #include "gkr_tuning.hpp"
+#include "gkr_vpd.hpp"
 
 namespace gkr {
 
@@ -404,7 +405,8 @@ void Program::state_import(DevState* S, const uint8_t* in) {
 
 void Program::run(hipStream_t s) const {
   for (const Step& st : steps) {
-    if (st.type >= ST_GL_FORWARD) launch_gl_step(st, s);
+    if (st.type >= ST_VPD_POWERS) launch_vpd_step(st, s);
+    else if (st.type >= ST_GL_FORWARD) launch_gl_step(st, s);
     else if (st.type >= ST_G_GATHER) launch_general_step(st, s);
     else launch_step(st, s);
   }
@@ -551,6 +553,37 @@ void emit_prove_circuit(Program& pg, const gkr_circuit& c, const Workspace& w, c
                w.chal + host_chal_index_ry(c, i), proof, tun);
     proof += layer_proof_words(c, i);
   }
+}
+
+// The proof of gkr_prove_circuit_committed: the inputs are committed
+// (Section 2.4) before the statement is bound, the statement absorbs the
+// commitment root in place of the input digest, the layers are proved as in
+// emit_prove_circuit, and the commitment is opened at the last layer's two
+// points. Proof: root (32 bytes) || layers || opening.
+void emit_prove_committed(Program& pg, const gkr_circuit& c, const Workspace& w, const VpdPlan& vp, void* vbase,
+                          const gkr_fr* d_inputs, uint64_t seed, gkr_fr* d_outputs, uint8_t* d_proof,
+                          const Tuning& tun) {
+  const uint32_t d = c.depth;
+  pg.to_mont(d_inputs, w.layer[d], 1ull << c.s(d));
+  emit_forward(pg, c, w);
+  pg.from_mont(w.layer[0], d_outputs, 1ull << c.s(0));
+  emit_vpd_commit(pg, vp, vbase, w.layer[d]);
+  emit_vpd_root_out(pg, vp, vbase, d_proof);
+  pg.digest(d_outputs, 1ull << c.s(0), w.dig_out, w);
+  pg.transcript_begin(w.state, seed_state(seed), c.digest, vpd_root_words(vp, vbase), w.dig_out);
+  emit_output_claim(pg, c, w, tun);
+  uint32_t* proof = reinterpret_cast<uint32_t*>(d_proof + 32);
+  DevState* S = w.state;
+  for (uint32_t i = 0; i < d; ++i) {
+    const Fr* u = (i == 0) ? w.chal : w.chal + host_chal_index_rx(c, i - 1);
+    const Fr* v = (i == 0) ? w.chal : w.chal + host_chal_index_ry(c, i - 1);
+    const Fr* vu = (i == 0) ? &S->scratch[0] : &S->vx;
+    emit_layer(pg, c, i, w, w.layer[i + 1], u, v, vu, &S->vy, w.chal + host_chal_index_rx(c, i),
+               w.chal + host_chal_index_ry(c, i), proof, tun);
+    proof += layer_proof_words(c, i);
+  }
+  emit_vpd_open(pg, vp, vbase, w.layer[d], S, w.chal + host_chal_index_rx(c, d - 1),
+                w.chal + host_chal_index_ry(c, d - 1), c.sigma[d], c.n, reinterpret_cast<uint8_t*>(proof));
 }
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -940,6 +973,116 @@ int32_t gkr_prove_circuit(const gkr_circuit* c, const gkr_fr* d_inputs, uint64_t
       Workspace w = bind_workspace(*c, d_ws);
       emit_prove_circuit(pg, *c, w, d_inputs, seed, d_outputs, d_proof, current_tuning());
     }
+    pg.run(static_cast<hipStream_t>(stream));
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return GKR_ENOMEM;
+  }
+  return check_launch();
+}
+
+// ---------------------------------------------------------------- committed inputs
+
+static int32_t check_committed(const gkr_circuit* c, uint32_t queries) {
+  if (!c) {
+    set_error("null circuit");
+    return GKR_EINVAL;
+  }
+  if (c->general || c->field != GKR_FIELD_BN254) {
+    set_error("committed proofs cover layered circuits over BN254");
+    return GKR_EUNSUPPORTED;
+  }
+  if (c->depth < 1) {
+    set_error("a committed proof needs at least one gate layer");
+    return GKR_EINVAL;
+  }
+  const uint32_t s = c->s(c->depth);
+  if (s < 1 || s > kVpdMaxLogN) {
+    set_error("the commitment takes 2^1 .. 2^" + std::to_string(kVpdMaxLogN) + " inputs, not 2^" + std::to_string(s));
+    return GKR_EUNSUPPORTED;
+  }
+  if (queries < 1 || queries > GKR_MAX_QUERIES) {
+    set_error("queries must be in 1 .. " + std::to_string(GKR_MAX_QUERIES));
+    return GKR_EINVAL;
+  }
+  return GKR_OK;
+}
+
+int32_t gkr_committed_sizes(const gkr_circuit* c, uint32_t queries, size_t* ws_bytes, size_t* proof_bytes) {
+  if (int32_t rc = check_committed(c, queries)) return rc;
+  const VpdPlan vp = plan_vpd(c->s(c->depth), queries, c->n);
+  if (ws_bytes) *ws_bytes = ((c->plan.total + 255) & ~(size_t)255) + vp.total;
+  if (proof_bytes) *proof_bytes = 32 + gkr_proof_bytes(c) + vpd_opening_bytes(vp.s, queries);
+  return GKR_OK;
+}
+
+int32_t gkr_prove_circuit_committed(const gkr_circuit* c, const gkr_fr* d_inputs, uint64_t seed, uint32_t queries,
+                                    gkr_fr* d_outputs, uint8_t* d_proof, size_t proof_cap, void* d_ws,
+                                    size_t ws_bytes, void* stream) {
+  if (int32_t rc = check_committed(c, queries)) return rc;
+  if (!d_inputs || !d_outputs || !d_proof || !aligned16(d_inputs) || !aligned16(d_outputs) || !aligned16(d_proof)) {
+    set_error("null or misaligned argument");
+    return GKR_EINVAL;
+  }
+  size_t need_ws = 0, need_proof = 0;
+  gkr_committed_sizes(c, queries, &need_ws, &need_proof);
+  if (proof_cap < need_proof) {
+    set_error("proof buffer too small: " + std::to_string(proof_cap) + " < " + std::to_string(need_proof));
+    return GKR_EBUFSZ;
+  }
+  if (int32_t rc = check_ws(c, d_ws, ws_bytes)) return rc;
+  if (ws_bytes < need_ws) {
+    set_error("workspace too small: " + std::to_string(ws_bytes) + " < " + std::to_string(need_ws));
+    return GKR_EBUFSZ;
+  }
+  try {
+    Program pg;
+    Workspace w = bind_workspace(*c, d_ws);
+    const VpdPlan vp = plan_vpd(c->s(c->depth), queries, c->n);
+    void* vbase = static_cast<char*>(d_ws) + ((c->plan.total + 255) & ~(size_t)255);
+    emit_prove_committed(pg, *c, w, vp, vbase, d_inputs, seed, d_outputs, d_proof, current_tuning());
+    pg.run(static_cast<hipStream_t>(stream));
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return GKR_ENOMEM;
+  }
+  return check_launch();
+}
+
+int32_t gkr_vpd_workspace_bytes(uint32_t log_n, size_t* bytes) {
+  if (log_n < 1 || log_n > kVpdMaxLogN) {
+    set_error("the commitment takes 2^1 .. 2^" + std::to_string(kVpdMaxLogN) + " values");
+    return GKR_EUNSUPPORTED;
+  }
+  if (bytes) *bytes = (((sizeof(Fr) << log_n) + 255) & ~(size_t)255) + plan_vpd(log_n, 1, 0).total;
+  return GKR_OK;
+}
+
+int32_t gkr_vpd_commit(uint32_t log_n, const gkr_fr* d_values, uint8_t* d_root, void* d_ws, size_t ws_bytes,
+                       void* stream) {
+  size_t need = 0;
+  if (int32_t rc = gkr_vpd_workspace_bytes(log_n, &need)) return rc;
+  if (!d_values || !d_root || !d_ws || !aligned16(d_values) || !aligned16(d_ws)) {
+    set_error("null or misaligned argument");
+    return GKR_EINVAL;
+  }
+  if (ws_bytes < need) {
+    set_error("workspace too small: " + std::to_string(ws_bytes) + " < " + std::to_string(need));
+    return GKR_EBUFSZ;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+    set_error("no HIP device");
+    return GKR_EDEVICE;
+  }
+  try {
+    Program pg;
+    Fr* mont = static_cast<Fr*>(d_ws);
+    void* vbase = static_cast<char*>(d_ws) + (((sizeof(Fr) << log_n) + 255) & ~(size_t)255);
+    const VpdPlan vp = plan_vpd(log_n, 1, 0);
+    pg.to_mont(d_values, mont, 1ull << log_n);
+    emit_vpd_commit(pg, vp, vbase, mont);
+    emit_vpd_root_out(pg, vp, vbase, d_root);
     pg.run(static_cast<hipStream_t>(stream));
   } catch (const std::bad_alloc&) {
     set_error("host allocation failed");

@@ -107,7 +107,25 @@ enum StepType : uint32_t {
   ST_GL_P2,
   ST_GL_ROUND,
   ST_GL_TAIL,
-  ST_GL_END
+  ST_GL_END,
+  // The commitment to the input layer and its opening: launched by
+  // launch_vpd_step, plain path only.
+  ST_VPD_POWERS = 128,
+  ST_VPD_TWIDDLES,
+  ST_VPD_SCALE,
+  ST_VPD_NTT,
+  ST_VPD_MUL,
+  ST_VPD_LEAVES,
+  ST_VPD_NODES,
+  ST_VPD_TREE_TOP,
+  ST_VPD_BEGIN,
+  ST_VPD_ABSORB,
+  ST_VPD_ROOT_OUT,
+  ST_VPD_FOLD0,
+  ST_VPD_FOLD,
+  ST_VPD_FINAL,
+  ST_VPD_QUERIES,
+  ST_VPD_END
 };
 
 struct Step {

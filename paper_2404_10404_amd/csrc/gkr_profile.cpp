@@ -36,7 +36,8 @@ const char* kNames[PC_COUNT] = {"forward",        "digest",         "transcript"
                                 "tail",           "tail_sub",       "phase2_tables", "copy_contract",
                                 "local_contract", "small",          "convert",       "batch",
                                 "g_gather",       "g_forward",      "g_claim_tables", "g_phase1_init",
-                                "g_phase2_tables"};
+                                "g_phase2_tables", "vpd_ntt",        "vpd_merkle",    "vpd_fri",
+                                "vpd_other"};
 
 hipEvent_t get_event() {
   if (!g_pool.empty()) {

@@ -27,6 +27,10 @@ enum ProfClass {
   PC_G_CLAIMS,
   PC_G_PHASE1_INIT,
   PC_G_PHASE2_TABLES,
+  PC_VPD_NTT,
+  PC_VPD_MERKLE,
+  PC_VPD_FRI,
+  PC_VPD_OTHER,
   PC_COUNT
 };
 

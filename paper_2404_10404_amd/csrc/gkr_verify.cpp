@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <string>
 #include <thread>
 #include <vector>
@@ -20,6 +21,7 @@
 #include "gkr_general.hpp"
 #include "gkr_gl.hpp"
 #include "gkr_internal.hpp"
+#include "gkr_vpd.hpp"
 #include "gl.hpp"
 
 namespace gkr {
@@ -530,6 +532,276 @@ extern "C" int32_t gkr_gl_verify(const gkr_circuit* c, const uint64_t* inputs, c
   }
 }
 
+namespace gkr {
+namespace {
+
+HostTranscript layered_statement(const gkr_circuit* c, uint64_t seed, const uint32_t input_digest[8],
+                                 const gkr_fr* outputs) {
+  HostTranscript tr;
+  uint8_t msg[19];
+  memcpy(msg, "SISU-GKR-v1", 11);
+  for (int k = 0; k < 8; ++k) msg[11 + k] = (uint8_t)(seed >> (8 * k));
+  sha256_bytes(msg, sizeof(msg), tr.st.h);
+  uint32_t dig[8];
+  tr.absorb_words(kTagDigest, c->digest, 8);
+  tr.absorb_words(kTagDigest, input_digest, 8);
+  tree_digest_host(reinterpret_cast<const uint8_t*>(outputs), (1ull << c->s(0)) * 32, dig);
+  tr.absorb_words(kTagDigest, dig, 8);
+  return tr;
+}
+
+// The layer-by-layer checks of a layered proof (pf: canonical elements),
+// from the output claim down to the two claims on the input layer: false if
+// a round check or a layer's final check fails. Leaves the input layer's
+// points (Montgomery) in u, v and their claimed values in vu, vv.
+bool verify_layers(const gkr_circuit* c, HostTranscript& tr, const gkr_fr* outputs, const Fr* pf,
+                   std::vector<Fr>& u, std::vector<Fr>& v, Fr& vu, Fr& vv) {
+  const uint32_t d = c->depth, n = c->n;
+  uint64_t pos = 0;
+  u.assign(c->s(0), fr_zero());
+  v.clear();
+  for (auto& x : u) x = to_m(tr.squeeze());
+  vu = mle_host(outputs, c->s(0), u.data());
+  vv = fr_zero();
+  bool accept = true;
+  for (uint32_t i = 0; i < d; ++i) {
+    Fr alpha = fr_one(), beta = fr_zero();
+    if (i > 0) {
+      alpha = to_m(tr.squeeze());
+      beta = to_m(tr.squeeze());
+    }
+    Fr claim = fr_add(fr_mul(alpha, vu), fr_mul(beta, vv));
+    const uint32_t s1 = c->s(i + 1), sg = c->sigma[i], sg1 = c->sigma[i + 1];
+    std::vector<Fr> rxy[2];
+    Fr vals[2];
+    for (int phase = 0; phase < 2; ++phase) {
+      for (uint32_t j = 0; j < s1; ++j) {
+        const Fr* e = pf + pos;
+        pos += 3;
+        const Fr e0 = to_m(e[0]), e1 = to_m(e[1]), e2 = to_m(e[2]);
+        if (!fr_eq(fr_add(e0, e1), claim)) accept = false;
+        const Fr r = to_m(tr.round_challenge(e));
+        rxy[phase].push_back(r);
+        claim = fr_interp3(e0, e1, e2, r);
+      }
+      vals[phase] = to_m(pf[pos]);
+      tr.absorb_elements(kTagValue, pf + pos, 1);
+      pos += 1;
+    }
+    const std::vector<Fr>& rx = rxy[0];
+    const std::vector<Fr>& ry = rxy[1];
+    // predicates
+    const std::vector<Fr> elx = eq_table_host(rx.data(), sg1), ely = eq_table_host(ry.data(), sg1);
+    const std::vector<Fr> wu = eq_table_host(u.data(), sg);
+    const Fr cu = triple_eq(u.data() + sg, rx.data() + sg1, ry.data() + sg1, n);
+    std::vector<Fr> wv;
+    Fr cv = fr_zero();
+    if (i > 0) {
+      wv = eq_table_host(v.data(), sg);
+      cv = triple_eq(v.data() + sg, rx.data() + sg1, ry.data() + sg1, n);
+    }
+    Fr add_v = fr_zero(), mul_v = fr_zero();
+    const std::vector<gkr_gate>& gl = c->gates[i];
+    for (size_t z = 0; z < gl.size(); ++z) {
+      Fr wgt = fr_mul(fr_mul(alpha, wu[z]), cu);
+      if (i > 0) wgt = fr_add(wgt, fr_mul(fr_mul(beta, wv[z]), cv));
+      const Fr term = fr_mul(fr_mul(wgt, elx[gl[z].x]), ely[gl[z].y]);
+      if (gl[z].type == GKR_GATE_MUL) mul_v = fr_add(mul_v, term);
+      else add_v = fr_add(add_v, term);
+    }
+    const Fr vx = vals[0], vy = vals[1];
+    const Fr fin = fr_add(fr_mul(fr_mul(mul_v, vx), vy), fr_mul(add_v, fr_add(vx, vy)));
+    if (!fr_eq(fin, claim)) accept = false;
+    u = rx;
+    v = ry;
+    vu = vx;
+    vv = vy;
+  }
+  return accept;
+}
+
+// ---------------------------------------------------------------- committed inputs
+
+Fr q_weight_tensor(const std::vector<Fr>& r, const std::vector<Fr>& ypow) {
+  // prod_j ((1 - r_j) + r_j y^(2^(s-1-j)))
+  const size_t s = r.size();
+  Fr acc = fr_one();
+  for (size_t j = 0; j < s; ++j) acc = fr_mul(acc, fr_add(fr_one_minus(r[j]), fr_mul(r[j], ypow[s - 1 - j])));
+  return acc;
+}
+
+// q(x) = x^N Q(1/x) + (1 - x^N) Q(0), Q = Q_r1 + lam Q_r2 (Montgomery in and out).
+Fr q_at_host(const std::vector<Fr>& r1, const std::vector<Fr>& r2, const Fr& lam, const Fr& x, Fr& xN) {
+  const size_t s = r1.size();
+  std::vector<Fr> ypow(s + 1), xpow(s + 1);
+  ypow[0] = fr_inverse(x);
+  xpow[0] = x;
+  for (size_t k = 1; k <= s; ++k) {
+    ypow[k] = fr_mul(ypow[k - 1], ypow[k - 1]);
+    xpow[k] = fr_mul(xpow[k - 1], xpow[k - 1]);
+  }
+  xN = xpow[s];
+  std::vector<Fr> zero(s + 1, fr_zero());
+  const Fr qinv = fr_add(q_weight_tensor(r1, ypow), fr_mul(lam, q_weight_tensor(r2, ypow)));
+  const Fr q0 = fr_add(q_weight_tensor(r1, zero), fr_mul(lam, q_weight_tensor(r2, zero)));
+  return fr_add(fr_mul(xN, qinv), fr_mul(fr_one_minus(xN), q0));
+}
+
+uint32_t bitrev_host(uint64_t v, uint32_t bits) {
+  uint64_t r = 0;
+  for (uint32_t i = 0; i < bits; ++i) r |= ((v >> i) & 1) << (bits - 1 - i);
+  return (uint32_t)r;
+}
+
+// The domain point at position t of a bit-reversed table over shift <w_m>.
+Fr point_of_position(uint64_t t, uint32_t log_m, const Fr& shift) {
+  return fr_mul(shift, fr_pow_u64(vpd_root_of_unity(log_m), bitrev_host(t, log_m)));
+}
+
+struct ByteReader {
+  const uint8_t* p;
+  size_t len, pos = 0;
+  bool ok = true;
+  void raw(uint8_t* out, size_t k) {
+    if (pos + k > len) {
+      ok = false;
+      memset(out, 0, k);
+      return;
+    }
+    memcpy(out, p + pos, k);
+    pos += k;
+  }
+  // A canonical element (returned in Montgomery form); a non-canonical one fails the read.
+  Fr element() {
+    Fr a;
+    raw(reinterpret_cast<uint8_t*>(a.v), 32);
+    if (!fr_is_canonical(a)) {
+      ok = false;
+      return fr_zero();
+    }
+    return to_m(a);
+  }
+  // A digest as SHA-256 words (the bytes are big-endian words).
+  void digest(uint32_t w[8]) {
+    uint8_t b[32];
+    raw(b, 32);
+    for (int k = 0; k < 8; ++k)
+      w[k] = ((uint32_t)b[4 * k] << 24) | ((uint32_t)b[4 * k + 1] << 16) | ((uint32_t)b[4 * k + 2] << 8) | b[4 * k + 3];
+  }
+};
+
+Sha256Block pair_block_host(const Fr& a, const Fr& b) {
+  Sha256Block blk;
+  for (int k = 0; k < 8; ++k) {
+    blk.w[k] = bswap32(a.v[k]);
+    blk.w[8 + k] = bswap32(b.v[k]);
+  }
+  return blk;
+}
+
+// Root from a leaf digest and its bottom-up path.
+void root_from_path(Sha256State h, uint64_t u, ByteReader& rd, uint32_t depth, uint32_t out[8]) {
+  for (uint32_t lv = 0; lv < depth; ++lv) {
+    uint32_t sib[8];
+    rd.digest(sib);
+    Sha256Block blk;
+    for (int k = 0; k < 8; ++k) {
+      blk.w[k] = (u & 1) ? sib[k] : h.h[k];
+      blk.w[8 + k] = (u & 1) ? h.h[k] : sib[k];
+    }
+    h = sha256_compress_v(sha256_iv(), blk);
+    u >>= 1;
+  }
+  for (int k = 0; k < 8; ++k) out[k] = h.h[k];
+}
+
+bool same_words(const uint32_t* a, const uint32_t* b) {
+  for (int k = 0; k < 8; ++k)
+    if (a[k] != b[k]) return false;
+  return true;
+}
+
+// Fold of a pair (R(x), R(-x)) by beta: (a + b) / 2 + beta (a - b) / (2x).
+Fr fold_pair(const Fr& a, const Fr& b, const Fr& beta, const Fr& x) {
+  const Fr inv2 = fr_inv2();
+  return fr_add(fr_mul(fr_add(a, b), inv2), fr_mul(fr_mul(fr_mul(beta, fr_sub(a, b)), inv2), fr_inverse(x)));
+}
+
+// The opening of the commitment root_f at (r1, r2) with claims (c1, c2), all
+// Montgomery; continues the transcript.
+bool verify_opening(const uint32_t root_f[8], uint32_t s, const std::vector<Fr>& r1, const std::vector<Fr>& r2,
+                    const Fr& c1, const Fr& c2, HostTranscript& tr, ByteReader& rd, uint32_t queries) {
+  const uint32_t logM = s + kVpdLogBlowup, d0 = logM - 1;
+  const uint64_t M = 1ull << logM;
+  const Fr lam = to_m(tr.squeeze());
+  const Fr c = fr_add(c1, fr_mul(lam, c2));
+  uint32_t root_hg[8];
+  rd.digest(root_hg);
+  tr.absorb_words(kTagCommit, root_hg, 8);
+  Fr a[4];
+  for (auto& x : a) x = to_m(tr.squeeze());
+  std::vector<Fr> betas(s);
+  std::vector<std::array<uint32_t, 8>> roots(s > 0 ? s - 1 : 0);
+  for (uint32_t i = 0; i < s; ++i) {
+    betas[i] = to_m(tr.squeeze());
+    if (i + 1 < s) {
+      rd.digest(roots[i].data());
+      tr.absorb_words(kTagCommit, roots[i].data(), 8);
+    }
+  }
+  const Fr fin = rd.element();
+  {
+    const Fr canon = from_m(fin);
+    tr.absorb_elements(kTagValue, &canon, 1);
+  }
+  bool ok = rd.ok;
+  const Fr shift = vpd_shift();
+  for (uint32_t q = 0; q < queries && ok; ++q) {
+    const uint64_t u = tr.squeeze().v[0] & (M / 2 - 1);  // the canonical challenge mod M / 2
+    const Fr f0 = rd.element(), f1 = rd.element();
+    uint32_t rt[8];
+    root_from_path(sha256_compress_v(sha256_iv(), pair_block_host(f0, f1)), u, rd, d0, rt);
+    ok = ok && same_words(rt, root_f);
+    Fr hg[4];
+    for (auto& x : hg) x = rd.element();
+    Sha256State lh = sha256_compress_v(sha256_iv(), pair_block_host(hg[0], hg[1]));
+    lh = sha256_compress_v(lh, pair_block_host(hg[2], hg[3]));
+    root_from_path(lh, u, rd, d0, rt);
+    ok = ok && same_words(rt, root_hg);
+    const Fr x = point_of_position(2 * u, logM, shift);
+    Fr pair[2];
+    for (int side = 0; side < 2; ++side) {
+      const Fr xx = side ? fr_neg(x) : x;
+      const Fr fx = side ? f1 : f0, hx = hg[side], gx = hg[2 + side];
+      Fr xN;
+      const Fr qx = q_at_host(r1, r2, lam, xx, xN);
+      const Fr lhs = fr_mul(fx, qx);
+      const Fr rhs = fr_add(fr_add(c, fr_mul(xx, gx)), fr_mul(fr_sub(xN, fr_one()), hx));
+      ok = ok && fr_eq(lhs, rhs);
+      pair[side] = fr_add(fr_add(fr_mul(a[0], fx), fr_mul(a[1], hx)),
+                          fr_mul(side ? fr_sub(a[2], fr_mul(a[3], x)) : fr_add(a[2], fr_mul(a[3], x)), gx));
+    }
+    Fr cur = fold_pair(pair[0], pair[1], betas[0], x);
+    uint64_t pos = u;
+    Fr sh = fr_mul(shift, shift);
+    for (uint32_t i = 1; i < s; ++i) {
+      const Fr v0 = rd.element(), v1 = rd.element();
+      const uint64_t leaf = pos >> 1;
+      root_from_path(sha256_compress_v(sha256_iv(), pair_block_host(v0, v1)), leaf, rd, d0 - i, rt);
+      ok = ok && same_words(rt, roots[i - 1].data());
+      ok = ok && fr_eq((pos & 1) ? v1 : v0, cur);
+      cur = fold_pair(v0, v1, betas[i], point_of_position(2 * leaf, logM - i, sh));
+      pos = leaf;
+      sh = fr_mul(sh, sh);
+    }
+    ok = ok && fr_eq(cur, fin) && rd.ok;
+  }
+  return ok && rd.ok && rd.pos == rd.len;
+}
+
+}  // namespace
+}  // namespace gkr
+
 extern "C" int32_t gkr_verify(const gkr_circuit* c, const gkr_fr* inputs, const gkr_fr* outputs,
                               uint64_t seed, const uint8_t* proof, size_t proof_len) {
   try {
@@ -542,7 +814,7 @@ extern "C" int32_t gkr_verify(const gkr_circuit* c, const gkr_fr* inputs, const 
       set_error("this circuit is over the Goldilocks field: use gkr_gl_verify");
       return GKR_EINVAL;
     }
-    const uint32_t d = c->depth, n = c->n;
+    const uint32_t d = c->depth;
     size_t need = 0;
     for (uint32_t i = 0; i < d; ++i) need += (6ull * c->s(i + 1) + 2) * 32;
     if (proof_len != need) {
@@ -554,80 +826,12 @@ extern "C" int32_t gkr_verify(const gkr_circuit* c, const gkr_fr* inputs, const 
       set_error("element not canonical");
       return GKR_EINVAL;
     }
-    const Fr* pf = reinterpret_cast<const Fr*>(proof);
-    uint64_t pos = 0;
-
-    HostTranscript tr;
-    {
-      uint8_t msg[19];
-      memcpy(msg, "SISU-GKR-v1", 11);
-      for (int k = 0; k < 8; ++k) msg[11 + k] = (uint8_t)(seed >> (8 * k));
-      sha256_bytes(msg, sizeof(msg), tr.st.h);
-    }
     uint32_t dig[8];
-    tr.absorb_words(kTagDigest, c->digest, 8);
     tree_digest_host(reinterpret_cast<const uint8_t*>(inputs), nin * 32, dig);
-    tr.absorb_words(kTagDigest, dig, 8);
-    tree_digest_host(reinterpret_cast<const uint8_t*>(outputs), nout * 32, dig);
-    tr.absorb_words(kTagDigest, dig, 8);
-
-    std::vector<Fr> u(c->s(0)), v;
-    for (auto& x : u) x = to_m(tr.squeeze());
-    Fr vu = mle_host(outputs, c->s(0), u.data()), vv = fr_zero();
-    bool accept = true;
-    for (uint32_t i = 0; i < d; ++i) {
-      Fr alpha = fr_one(), beta = fr_zero();
-      if (i > 0) {
-        alpha = to_m(tr.squeeze());
-        beta = to_m(tr.squeeze());
-      }
-      Fr claim = fr_add(fr_mul(alpha, vu), fr_mul(beta, vv));
-      const uint32_t s1 = c->s(i + 1), sg = c->sigma[i], sg1 = c->sigma[i + 1];
-      std::vector<Fr> rxy[2];
-      Fr vals[2];
-      for (int phase = 0; phase < 2; ++phase) {
-        for (uint32_t j = 0; j < s1; ++j) {
-          const Fr* e = pf + pos;
-          pos += 3;
-          const Fr e0 = to_m(e[0]), e1 = to_m(e[1]), e2 = to_m(e[2]);
-          if (!fr_eq(fr_add(e0, e1), claim)) accept = false;
-          const Fr r = to_m(tr.round_challenge(e));
-          rxy[phase].push_back(r);
-          claim = fr_interp3(e0, e1, e2, r);
-        }
-        vals[phase] = to_m(pf[pos]);
-        tr.absorb_elements(kTagValue, pf + pos, 1);
-        pos += 1;
-      }
-      const std::vector<Fr>& rx = rxy[0];
-      const std::vector<Fr>& ry = rxy[1];
-      // predicates
-      const std::vector<Fr> elx = eq_table_host(rx.data(), sg1), ely = eq_table_host(ry.data(), sg1);
-      const std::vector<Fr> wu = eq_table_host(u.data(), sg);
-      const Fr cu = triple_eq(u.data() + sg, rx.data() + sg1, ry.data() + sg1, n);
-      std::vector<Fr> wv;
-      Fr cv = fr_zero();
-      if (i > 0) {
-        wv = eq_table_host(v.data(), sg);
-        cv = triple_eq(v.data() + sg, rx.data() + sg1, ry.data() + sg1, n);
-      }
-      Fr add_v = fr_zero(), mul_v = fr_zero();
-      const std::vector<gkr_gate>& gl = c->gates[i];
-      for (size_t z = 0; z < gl.size(); ++z) {
-        Fr wgt = fr_mul(fr_mul(alpha, wu[z]), cu);
-        if (i > 0) wgt = fr_add(wgt, fr_mul(fr_mul(beta, wv[z]), cv));
-        const Fr term = fr_mul(fr_mul(wgt, elx[gl[z].x]), ely[gl[z].y]);
-        if (gl[z].type == GKR_GATE_MUL) mul_v = fr_add(mul_v, term);
-        else add_v = fr_add(add_v, term);
-      }
-      const Fr vx = vals[0], vy = vals[1];
-      const Fr fin = fr_add(fr_mul(fr_mul(mul_v, vx), vy), fr_mul(add_v, fr_add(vx, vy)));
-      if (!fr_eq(fin, claim)) accept = false;
-      u = rx;
-      v = ry;
-      vu = vx;
-      vv = vy;
-    }
+    HostTranscript tr = layered_statement(c, seed, dig, outputs);
+    std::vector<Fr> u, v;
+    Fr vu, vv;
+    bool accept = verify_layers(c, tr, outputs, reinterpret_cast<const Fr*>(proof), u, v, vu, vv);
     if (accept) {
       if (!fr_eq(vu, mle_host(inputs, c->s(d), u.data()))) accept = false;
       if (accept && !fr_eq(vv, mle_host(inputs, c->s(d), v.data()))) accept = false;
@@ -638,3 +842,40 @@ extern "C" int32_t gkr_verify(const gkr_circuit* c, const gkr_fr* inputs, const 
     return GKR_ENOMEM;
   }
 }
+
+extern "C" int32_t gkr_verify_committed(const gkr_circuit* c, const gkr_fr* outputs, uint64_t seed, uint32_t queries,
+                                        const uint8_t* proof, size_t proof_len) {
+  try {
+    if (!c || !outputs || !proof) {
+      set_error("null argument");
+      return GKR_EINVAL;
+    }
+    size_t need = 0;
+    if (int32_t rc = gkr_committed_sizes(c, queries, nullptr, &need)) return rc;
+    if (proof_len != need) {
+      set_error("proof length " + std::to_string(proof_len) + ", expected " + std::to_string(need));
+      return GKR_EINVAL;
+    }
+    const uint32_t d = c->depth;
+    size_t gkr_len = 0;
+    for (uint32_t i = 0; i < d; ++i) gkr_len += (6ull * c->s(i + 1) + 2) * 32;
+    if (!canonical_all(outputs, 1ull << c->s(0)) || !canonical_all(proof + 32, gkr_len / 32)) {
+      set_error("element not canonical");
+      return GKR_EINVAL;
+    }
+    ByteReader head{proof, 32};
+    uint32_t root[8];
+    head.digest(root);
+    HostTranscript tr = layered_statement(c, seed, root, outputs);
+    std::vector<Fr> u, v;
+    Fr vu, vv;
+    const bool layers_ok = verify_layers(c, tr, outputs, reinterpret_cast<const Fr*>(proof + 32), u, v, vu, vv);
+    ByteReader rd{proof + 32 + gkr_len, proof_len - 32 - gkr_len};
+    const bool open_ok = verify_opening(root, c->s(d), u, v, vu, vv, tr, rd, queries);
+    return (layers_ok && open_ok) ? 1 : 0;
+  } catch (...) {
+    set_error("verifier failure (allocation)");
+    return GKR_ENOMEM;
+  }
+}
+

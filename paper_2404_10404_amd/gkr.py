@@ -119,6 +119,16 @@ def lib() -> ctypes.CDLL:
         L.gkr_prove_circuit_noalloc.restype = _i32
         L.gkr_ubench.argtypes = [_u32, _u32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.gkr_ubench.restype = _i32
+        L.gkr_committed_sizes.argtypes = [_vp, _u32, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]
+        L.gkr_committed_sizes.restype = _i32
+        L.gkr_prove_circuit_committed.argtypes = [_vp, _vp, _u64, _u32, _vp, _vp, _sz, _vp, _sz, _vp]
+        L.gkr_prove_circuit_committed.restype = _i32
+        L.gkr_verify_committed.argtypes = [_vp, _vp, _u64, _u32, _vp, _sz]
+        L.gkr_verify_committed.restype = _i32
+        L.gkr_vpd_workspace_bytes.argtypes = [_u32, ctypes.POINTER(_sz)]
+        L.gkr_vpd_workspace_bytes.restype = _i32
+        L.gkr_vpd_commit.argtypes = [_u32, _vp, _vp, _vp, _sz, _vp]
+        L.gkr_vpd_commit.restype = _i32
         _lib = L
         _apply_tuning_cache(L)
     return _lib
@@ -392,6 +402,66 @@ class Prover:
 
     def proof_bytes(self) -> bytes:
         return bytes(self.proof[: self.c.proof_bytes].cpu().numpy().tobytes())
+
+
+# ------------------------------------------------------------ committed inputs
+
+DEFAULT_QUERIES = 64
+
+
+def committed_sizes(c: Circuit, queries: int = DEFAULT_QUERIES):
+    """(workspace bytes, proof bytes) of a committed-input proof."""
+    ws, pb = _sz(0), _sz(0)
+    _check(lib().gkr_committed_sizes(c.handle, queries, ctypes.byref(ws), ctypes.byref(pb)))
+    return ws.value, pb.value
+
+
+def prove_circuit_committed(c: Circuit, d_inputs, seed: int, queries: int, d_outputs, d_proof, d_ws,
+                            stream=None) -> None:
+    """gkr_prove_circuit_committed on caller tensors."""
+    _check(lib().gkr_prove_circuit_committed(c.handle, _ptr(d_inputs), seed & (2**64 - 1), queries,
+                                             _ptr(d_outputs), _ptr(d_proof),
+                                             d_proof.numel() * d_proof.element_size(), _ptr(d_ws),
+                                             d_ws.numel() * d_ws.element_size(), _stream(stream)))
+
+
+def verify_committed(c: Circuit, outputs, seed: int, proof: bytes, queries: int = DEFAULT_QUERIES) -> int:
+    """gkr_verify_committed on host buffers (the outputs only): 1 accept, 0 reject."""
+    b = _elements(outputs)
+    pb = np.frombuffer(bytes(proof), dtype=np.uint8)
+    return _check(lib().gkr_verify_committed(c.handle, b.ctypes.data, seed & (2**64 - 1), queries,
+                                             pb.ctypes.data if pb.size else None, pb.size))
+
+
+def vpd_workspace_bytes(log_n: int) -> int:
+    n = _sz(0)
+    _check(lib().gkr_vpd_workspace_bytes(log_n, ctypes.byref(n)))
+    return n.value
+
+
+def vpd_commit(log_n: int, d_values, d_root, d_ws, stream=None) -> None:
+    """gkr_vpd_commit: the 32-byte root of the commitment to 2^log_n values."""
+    _check(lib().gkr_vpd_commit(log_n, _ptr(d_values), _ptr(d_root), _ptr(d_ws),
+                                d_ws.numel() * d_ws.element_size(), _stream(stream)))
+
+
+class CommittedProver:
+    """Device buffers of one committed-input proof at a time for one circuit."""
+
+    def __init__(self, c: Circuit, queries: int = DEFAULT_QUERIES, device="cuda"):
+        import torch
+        self.c = c
+        self.queries = queries
+        ws, self.nbytes = committed_sizes(c, queries)
+        self.ws = alloc_bytes(ws, device)
+        self.proof = alloc_bytes(self.nbytes, device)
+        self.outputs = torch.empty((1 << c.s(0), 8), dtype=torch.int32, device=device)
+
+    def prove(self, d_inputs, seed: int, stream=None) -> None:
+        prove_circuit_committed(self.c, d_inputs, seed, self.queries, self.outputs, self.proof, self.ws, stream)
+
+    def proof_bytes(self) -> bytes:
+        return bytes(self.proof[: self.nbytes].cpu().numpy().tobytes())
 
 
 # ------------------------------------------------------------ batched proving

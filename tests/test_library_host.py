@@ -216,3 +216,61 @@ def test_host_goldilocks_verifier_accepts_oracle_proofs(shape):
         assert gkr.gl_verify(c, inputs, outs, seed, bytes(bad)) in (0, gkr.GKR_EINVAL), k
     with pytest.raises(gkr.GkrError):
         gkr.verify(c, gs.make_inputs(spec), gs.make_inputs(spec)[:1 << c.s(0)], seed, proof)
+
+
+@pytest.mark.parametrize("shape,queries", [((1, 0, (2, 3), 301), 8), ((3, 2, (3, 4, 3, 4), 302), 64),
+                                           ((2, 3, (2, 1, 3), 303), 1), ((1, 0, (1, 1), 304), 5)])
+def test_host_committed_verifier_accepts_oracle_proofs(shape, queries):
+    """The library's sizes and verifier of committed-input proofs agree with the
+    oracle (oracle/vpd.py): honest proofs are accepted from the outputs alone,
+    and a flipped bit in each 32-byte unit of the opening is rejected."""
+    from oracle import vpd
+    depth, n, sig, seed = shape
+    spec = gs.CircuitSpec(depth=depth, log_copies=n, log_sub_width=tuple(sig), mu=(1, 2), seed=seed)
+    wiring = gs.make_wiring(spec)
+    oc_ = oc.Circuit.from_synth(spec, wiring)
+    pf = vpd.prove_committed(oc_, gs.elements_to_ints(gs.make_inputs(spec)), seed, queries)
+    proof = pf.proof_bytes()
+    c = gkr.Circuit.from_synth(spec, wiring)
+    _, pbytes = gkr.committed_sizes(c, queries)
+    assert pbytes == len(proof) == vpd.committed_proof_length(oc_, queries)
+    outs = gs.ints_to_elements(pf.outputs)
+    assert gkr.verify_committed(c, outs, seed, proof, queries) == 1
+    gkr_end = 32 + c.proof_bytes
+    for off in [0] + list(range(gkr_end, len(proof), 32 * max(1, (len(proof) - gkr_end) // 32 // 60))):
+        bad = bytearray(proof)
+        bad[off] ^= 1
+        assert gkr.verify_committed(c, outs, seed, bytes(bad), queries) in (0, gkr.GKR_EINVAL), off
+    wrong = np.array(outs)
+    wrong[0, 0] ^= 1
+    assert gkr.verify_committed(c, wrong, seed, proof, queries) == 0
+    with pytest.raises(gkr.GkrError):
+        gkr.verify_committed(c, outs, seed, proof[:-32], queries)
+
+
+def test_committed_refusals():
+    """Committed proofs take layered BN254 circuits with 2^1 .. 2^26 inputs and
+    1 .. 256 queries; everything else is refused with a status, not a crash."""
+    spec = gs.CircuitSpec(depth=1, log_copies=0, log_sub_width=(2, 3), mu=(1, 2), seed=1)
+    c = gkr.Circuit.from_synth(spec, gs.make_wiring(spec))
+    assert gkr.committed_sizes(c, 1)[1] > 0 and gkr.committed_sizes(c, 256)[1] > 0
+    for q in (0, 257):
+        with pytest.raises(gkr.GkrError):
+            gkr.committed_sizes(c, q)
+    zero = gs.CircuitSpec(depth=1, log_copies=0, log_sub_width=(1, 0), mu=(1, 2), seed=1)
+    cz = gkr.Circuit.from_synth(zero, gs.make_wiring(zero))
+    with pytest.raises(gkr.GkrError) as e:
+        gkr.committed_sizes(cz, 8)
+    assert e.value.code == gkr.GKR_EUNSUPPORTED
+    cgl = gkr.Circuit.from_synth(spec, gs.make_wiring(spec), field=gkr.FIELD_GOLDILOCKS)
+    with pytest.raises(gkr.GkrError):
+        gkr.committed_sizes(cgl, 8)
+    gspec = gs.GeneralSpec(depth=2, log_copies=1, log_sub_width=(2, 3, 2), max_fanin=2, reach=2, cross=(1, 2), seed=3)
+    cg = gkr.GeneralCircuit.from_synth(gspec, gs.make_general_wiring(gspec))
+    with pytest.raises(gkr.GkrError):
+        gkr.committed_sizes(cg, 8)
+    with pytest.raises(gkr.GkrError):
+        gkr.vpd_workspace_bytes(0)
+    with pytest.raises(gkr.GkrError):
+        gkr.vpd_workspace_bytes(27)
+    assert gkr.vpd_workspace_bytes(26) > (32 << 28)

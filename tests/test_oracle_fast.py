@@ -50,3 +50,14 @@ def test_limb_verifier_matches_int_verifier():
     assert not ov.verify_limbs(c, limbs, outs, spec.seed, bytes(bad))
     outs[3, 0] ^= 1
     assert not ov.verify_limbs(c, limbs, outs, spec.seed, proof)
+
+
+def test_poly_eval_matches_horner_in_python():
+    """The blocked C Horner evaluation against plain Python Horner, across block
+    boundaries (2^16 coefficients per block) and at x = 0, 1, -1."""
+    from oracle import vpd
+    for count in (1, 3, 1 << 16, (1 << 16) + 5):
+        limbs = gs.field_elements(gs.stream_key(6, gs.PURPOSE_INPUT, count % 97), count)
+        vals = gs.elements_to_ints(limbs)
+        for x in (0, 1, P - 1, R.randrange(P)):
+            assert fast.poly_eval_limbs(limbs, x) == vpd.poly_eval(vals, x)
