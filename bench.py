@@ -33,6 +33,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+import numpy as np  # noqa: E402
+
 import gkr_synth as gs  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
@@ -407,6 +409,65 @@ def goldilocks_leg(gkr, steps, warmup, profile_steps, mac_peak_tops, bn254_ms=No
     return out
 
 
+VPD_CLASS_KERNEL = {"vpd_ntt": "k_vpd_ntt", "vpd_fri": "k_vpd_fold", "vpd_merkle": "k_vpd_leaves"}
+VPD_KERNEL_SOURCES = ["fr.hpp", "sha256.hpp", "gkr_device.hpp", "gkr_kernels.hpp", "gkr_bodies.hpp", "gkr_vpd.hpp",
+                      "gkr_vpd.hip"]
+
+
+def committed_leg(gkr, steps, warmup, profile_steps, mac_peak_tops, plain_ms=None):
+    """The single-worker share with its 2^26 inputs committed (Section 2.4):
+    commitment, the layered proof and the opening at the last layer's two
+    points with 64 queries; ms per proof and its cost over the plain proof,
+    the commitment kernels by class with the dominant one's roofline, the
+    library's verifier (outputs only) on the proof, and the committed proof
+    of the 2^20-gate data-parallel circuit against the oracle's digest."""
+    import torch
+    spec = gs.worker_share_c3()
+    wiring = gs.make_wiring(spec)
+    c = gkr.Circuit.from_synth(spec, wiring)
+    queries = gkr.DEFAULT_QUERIES
+    prover = gkr.CommittedProver(c, queries)
+    d_in = gkr.device_elements(gs.make_inputs(spec))
+    for _ in range(warmup):
+        prover.prove(d_in, spec.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prover.prove(d_in, spec.seed)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    out = {"workload": "single-worker share with committed inputs: 2^12 copies x (depth 24, 2^14 gates/layer), "
+                       "2^26 inputs, coset of 2^28, %d queries" % queries,
+           "queries": queries, "ms_per_proof": round(dt * 1e3, 4),
+           "field_gates_per_s": round(c.gate_layers / dt, 1), "proof_bytes": prover.nbytes}
+    if plain_ms:
+        out["commitment_ms_over_plain_proof"] = round(dt * 1e3 - plain_ms, 4)
+    if profile_steps:
+        prof = profile_pass(gkr, prover, d_in, spec.seed, profile_steps)
+        vp = {k: v for k, v in prof.items() if k.startswith("vpd_")}
+        out["commitment_kernels_ms"] = {k: round(v["ms"], 4) for k, v in sorted(vp.items(), key=lambda kv: -kv[1]["ms"])}
+        out["roofline"] = roofline(vp, "vpd_c3", mac_peak_tops, class_kernel=VPD_CLASS_KERNEL,
+                                   sources=VPD_KERNEL_SOURCES)
+        out["kernels"] = {k: {"ms": round(v["ms"], 4), "launches": v["launches"]} for k, v in
+                          sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:10]}
+    proof = prover.proof_bytes()
+    outs = np.ascontiguousarray(gkr.host_elements(prover.outputs))
+    del prover, d_in
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    out["verified_by_host"] = gkr.verify_committed(c, outs, spec.seed, proof, queries) == 1
+    out["host_verify_s"] = round(time.perf_counter() - t0, 3)
+    gd = golden_digest("vpd_c2")
+    if gd is not None:
+        s2 = gs.data_parallel_c2()
+        c2 = gkr.Circuit.from_synth(s2, gs.make_wiring(s2))
+        p2 = gkr.CommittedProver(c2, queries)
+        p2.prove(gkr.device_elements(gs.make_inputs(s2)), s2.seed)
+        torch.cuda.synchronize()
+        out["c2_vs_oracle_golden"] = hashlib.sha256(p2.proof_bytes()).hexdigest() == gd
+    return out
+
+
 def golden_digest(name):
     p = os.path.join(ROOT, "tests", "golden", "%s_proof.json" % name)
     if not os.path.exists(p):
@@ -445,6 +506,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="leave out the serving leg")
     ap.add_argument("--no-general", action="store_true", help="leave out the general-circuit leg")
     ap.add_argument("--no-goldilocks", action="store_true", help="leave out the Goldilocks-field leg")
+    ap.add_argument("--no-committed", action="store_true", help="leave out the committed-input leg")
     ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serving", "copy", "ubench"])
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--jobs", type=int, default=256)
@@ -575,6 +637,14 @@ def main():
                                             peaks["mad_u64_u32_per_s"] / 1e12 if peaks else None,
                                             line["ms_per_step"] if args.workload == "c3" else None)
         exact["goldilocks_slice_vs_oracle_golden"] = line["goldilocks"].get("slice_2^4_copies_vs_oracle_golden")
+        torch.cuda.empty_cache()
+    if not args.no_committed:
+        log("committed-input leg")
+        line["committed"] = committed_leg(gkr, 3, 1, 0 if args.no_profile else 1,
+                                          peaks["mad_u64_u32_per_s"] / 1e12 if peaks else None,
+                                          line["ms_per_step"] if args.workload == "c3" else None)
+        exact["committed_c2_vs_oracle_golden"] = line["committed"].get("c2_vs_oracle_golden")
+        exact["committed_c3_verified"] = line["committed"]["verified_by_host"]
         torch.cuda.empty_cache()
     if not args.no_batched:
         log("batched leg: 64 uneven jobs")

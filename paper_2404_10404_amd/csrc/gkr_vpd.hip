@@ -281,14 +281,25 @@ __global__ void __launch_bounds__(kBlock) k_vpd_scale(Step st) {
 // 2^L over p0, in one pass through LDS. A workgroup takes a tile of 2^W rows
 // (the index bits L-j0-W .. L-j0-1) by 2^c columns (consecutive low bits),
 // W + c <= 11. Forward (u5 = 0): decimation in frequency, natural order in,
-// bit-reversed out: (a, b) -> (a + b, (a - b) w^k). Inverse (u5 = 1): the
-// stages undone in reverse order, (a, b) -> (a + b w^-k, a - b w^-k), then a
-// scale by w[0..7] when u4 has bit 8 set. Twiddles w^k = T[k << (j + tshift)]
-// with T[t] = w_{2^(L + tshift)}^t; w^-t = -T[n_T/2 - t].
+// bit-reversed out; stage j maps (a, b) at distance 2^(L-1-j) to
+// (a + b, (a - b) w^k). Inverse (u5 = 1): the stages undone in reverse order,
+// (a, b) -> (a + b w^-k, a - b w^-k), then a scale by w[0..7] when u4 has
+// bit 8 set. Twiddles w^k = T[k << (j + tshift)] with T[t] = w_{2^(L+tshift)}^t;
+// w^-t = -T[n_T/2 - t]. Stages go two at a time: a thread holds the four
+// elements that two consecutive stages combine (rows r, r + h/2, r + h,
+// r + 3h/2), so a pair of stages costs one LDS round trip and one barrier;
+// an odd last stage is a plain radix-2 step.
 // p0 x, p1 T, u0 L, u1 j0, u2 W, u3 c, u4 tshift (| 256: scale), u5 inverse, q0 n_T / 2.
 constexpr int kNttTile = 2048;
+constexpr int kNttThreads = 512;
 
-__global__ void __launch_bounds__(kBlock) k_vpd_ntt(Step st) {
+// v w^(+-1) for twiddle index t (no product when t = 0).
+__device__ __forceinline__ Fr tw_mul(const Fr& v, const Fr* T, uint64_t t, uint64_t halfT, bool inverse) {
+  if (t == 0) return v;
+  return inverse ? fr_neg(fr_mul(v, ldf(T, halfT - t))) : fr_mul(v, ldf(T, t));
+}
+
+__global__ void __launch_bounds__(kNttThreads) k_vpd_ntt(Step st) {
   __shared__ Fr tile[kNttTile];
   Fr* x = P<Fr*>(st, 0);
   const Fr* T = P<const Fr*>(st, 1);
@@ -300,40 +311,69 @@ __global__ void __launch_bounds__(kBlock) k_vpd_ntt(Step st) {
   const uint32_t lo = L - j0 - W;
   const uint32_t C = 1u << c;
   const uint32_t nelem = 1u << (W + c);
-  const uint64_t colgroups = 1ull << (lo - c);
-  const uint64_t colgroup = blockIdx.x & (colgroups - 1);
+  const uint64_t colgroup = blockIdx.x & ((1ull << (lo - c)) - 1);
   const uint64_t blk = blockIdx.x >> (lo - c);
   const uint64_t base = (blk << (L - j0)) + (colgroup << c);
-  for (uint32_t e = threadIdx.x; e < nelem; e += kBlock) {
+  for (uint32_t e = threadIdx.x; e < nelem; e += kNttThreads) {
     const uint32_t r = e >> c, col = e & (C - 1);
     tile[e] = ldf(x, base + ((uint64_t)r << lo) + col);
   }
   __syncthreads();
-  const uint32_t nbf = nelem >> 1;
-  for (uint32_t step = 0; step < W; ++step) {
-    const uint32_t jj = inverse ? (W - 1 - step) : step;  // stage j0 + jj
-    const uint32_t j = j0 + jj;
-    const uint32_t hr = 1u << (W - 1 - jj);
-    for (uint32_t bi = threadIdx.x; bi < nbf; bi += kBlock) {
-      const uint32_t col = bi & (C - 1), rr = bi >> c;
-      const uint32_t ra = (rr / hr) * 2 * hr + (rr % hr), rb = ra + hr;
-      const uint64_t k = ((uint64_t)(ra % hr) << lo) + (colgroup << c) + col;
-      const uint64_t t = k << (j + tshift);
-      const uint32_t ia = (ra << c) + col, ib = (rb << c) + col;
-      const Fr a = tile[ia], b = tile[ib];
-      if (!inverse) {
-        tile[ia] = fr_add(a, b);
-        tile[ib] = t ? fr_mul(fr_sub(a, b), ldf(T, t)) : fr_sub(a, b);
-      } else {
-        const Fr bw = t ? fr_mul(b, fr_neg(ldf(T, halfT - t))) : b;
-        tile[ia] = fr_add(a, bw);
-        tile[ib] = fr_sub(a, bw);
+  const uint32_t npairs = W / 2, nops = npairs + (W & 1);
+  for (uint32_t op = 0; op < nops; ++op) {
+    const uint32_t fo = inverse ? (nops - 1 - op) : op;  // position in the forward order
+    if (fo == npairs) {
+      // the odd last stage (jj = W - 1, distance one row)
+      const uint32_t j = j0 + W - 1;
+      for (uint32_t bi = threadIdx.x; bi < nelem / 2; bi += kNttThreads) {
+        const uint32_t col = bi & (C - 1), ra = (bi >> c) * 2;
+        const uint64_t t = ((colgroup << c) + col) << (j + tshift);
+        const uint32_t ia = (ra << c) + col, ib = ia + C;
+        const Fr a = tile[ia], b = tile[ib];
+        if (!inverse) {
+          tile[ia] = fr_add(a, b);
+          tile[ib] = tw_mul(fr_sub(a, b), T, t, halfT, false);
+        } else {
+          const Fr bw = tw_mul(b, T, t, halfT, true);
+          tile[ia] = fr_add(a, bw);
+          tile[ib] = fr_sub(a, bw);
+        }
+      }
+    } else {
+      const uint32_t jj = 2 * fo, j = j0 + jj;
+      const uint32_t sh2 = W - 2 - jj;  // h/2 = 2^sh2 rows, h = 2^(sh2 + 1)
+      const uint32_t h2 = 1u << sh2, hr = 2 * h2;
+      for (uint32_t g = threadIdx.x; g < nelem / 4; g += kNttThreads) {
+        const uint32_t col = g & (C - 1), gr = g >> c;
+        const uint32_t r0 = ((gr >> sh2) << (sh2 + 2)) + (gr & (h2 - 1));
+        const uint32_t i0 = (r0 << c) + col, i1 = ((r0 + h2) << c) + col;
+        const uint32_t i2 = ((r0 + hr) << c) + col, i3 = ((r0 + hr + h2) << c) + col;
+        const uint64_t ka = ((uint64_t)(gr & (h2 - 1)) << lo) + (colgroup << c) + col;
+        const uint64_t kb = ka + ((uint64_t)h2 << lo);
+        const uint64_t ta = ka << (j + tshift), tb = kb << (j + tshift), tc = ka << (j + 1 + tshift);
+        const Fr x0 = tile[i0], x1 = tile[i1], x2 = tile[i2], x3 = tile[i3];
+        if (!inverse) {
+          const Fr a0 = fr_add(x0, x2), a2 = tw_mul(fr_sub(x0, x2), T, ta, halfT, false);
+          const Fr a1 = fr_add(x1, x3), a3 = tw_mul(fr_sub(x1, x3), T, tb, halfT, false);
+          tile[i0] = fr_add(a0, a1);
+          tile[i1] = tw_mul(fr_sub(a0, a1), T, tc, halfT, false);
+          tile[i2] = fr_add(a2, a3);
+          tile[i3] = tw_mul(fr_sub(a2, a3), T, tc, halfT, false);
+        } else {
+          const Fr t1 = tw_mul(x1, T, tc, halfT, true), t3 = tw_mul(x3, T, tc, halfT, true);
+          const Fr b0 = fr_add(x0, t1), b1 = fr_sub(x0, t1), b2 = fr_add(x2, t3), b3 = fr_sub(x2, t3);
+          const Fr u2 = tw_mul(b2, T, ta, halfT, true), u3 = tw_mul(b3, T, tb, halfT, true);
+          tile[i0] = fr_add(b0, u2);
+          tile[i1] = fr_add(b1, u3);
+          tile[i2] = fr_sub(b0, u2);
+          tile[i3] = fr_sub(b1, u3);
+        }
       }
     }
     __syncthreads();
   }
   const Fr sc = words_fr(st.w);
-  for (uint32_t e = threadIdx.x; e < nelem; e += kBlock) {
+  for (uint32_t e = threadIdx.x; e < nelem; e += kNttThreads) {
     const uint32_t r = e >> c, col = e & (C - 1);
     const Fr v = do_scale ? fr_mul(tile[e], sc) : tile[e];
     stf(x, base + ((uint64_t)r << lo) + col, v);
@@ -587,7 +627,7 @@ void launch_vpd_step(const Step& st, hipStream_t s) {
     case ST_VPD_POWERS: k_vpd_powers<<<grid, block, 0, s>>>(st); break;
     case ST_VPD_TWIDDLES: k_vpd_twiddles<<<grid, block, 0, s>>>(st); break;
     case ST_VPD_SCALE: k_vpd_scale<<<grid, block, 0, s>>>(st); break;
-    case ST_VPD_NTT: k_vpd_ntt<<<grid, block, 0, s>>>(st); cls = PC_VPD_NTT; break;
+    case ST_VPD_NTT: k_vpd_ntt<<<grid, dim3(kNttThreads), 0, s>>>(st); cls = PC_VPD_NTT; break;
     case ST_VPD_MUL: k_vpd_mul<<<grid, block, 0, s>>>(st); break;
     case ST_VPD_LEAVES: k_vpd_leaves<<<grid, block, 0, s>>>(st); cls = PC_VPD_MERKLE; break;
     case ST_VPD_NODES: k_vpd_nodes<<<grid, block, 0, s>>>(st); cls = PC_VPD_MERKLE; break;

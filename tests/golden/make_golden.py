@@ -10,7 +10,8 @@ workload, the SHA-256 of the outputs and of the proof, and the proof itself
 "g1" is the general-circuit workload (accumulation gates, right inputs from
 up to four layers back, oracle/general.py); "g1slice" the same sub-circuit
 with 2^2 copies. "gl_c3slice" and "gl_c2" are the Goldilocks variant
-(oracle/goldilocks.py) of the c3 slice and of c2.
+(oracle/goldilocks.py) of the c3 slice and of c2. "vpd_c2" is the
+committed-input proof (oracle/vpd.py, 64 queries) of c2.
 """
 import hashlib
 import json
@@ -29,6 +30,7 @@ from oracle import circuit as oc  # noqa: E402
 from oracle import general as og  # noqa: E402
 from oracle import goldilocks as ogl  # noqa: E402
 from oracle import prover as op  # noqa: E402
+from oracle import vpd  # noqa: E402
 from oracle.field import encode_all  # noqa: E402
 
 CASES = {
@@ -97,7 +99,38 @@ def make_goldilocks(name):
     print(name, "done in %.1f s" % (time.time() - t0), flush=True)
 
 
+# committed-input proofs (oracle/vpd.py)
+COMMITTED_CASES = {
+    "vpd_c2": (gs.data_parallel_c2, 64),
+}
+
+
+def make_committed(name):
+    spec_fn, queries = COMMITTED_CASES[name]
+    spec = spec_fn()
+    t0 = time.time()
+    wiring = gs.make_wiring(spec)
+    inputs = gs.elements_to_ints(gs.make_inputs(spec))
+    pf = vpd.prove_committed(oc.Circuit.from_synth(spec, wiring), inputs, spec.seed, queries)
+    proof = pf.proof_bytes()
+    rec = {
+        "workload": name, "depth": spec.depth, "log_copies": spec.log_copies,
+        "log_sub_width": list(spec.log_sub_width), "mu": list(spec.mu), "seed": spec.seed, "queries": queries,
+        "root_hex": pf.root.hex(),
+        "outputs_sha256": hashlib.sha256(encode_all(pf.outputs)).hexdigest(),
+        "proof_sha256": hashlib.sha256(proof).hexdigest(),
+        "proof_len": len(proof),
+        "oracle_seconds": round(time.time() - t0, 1),
+        "writer": "tests/golden/make_golden.py (CPU oracle)",
+    }
+    with open(os.path.join(HERE, "%s_proof.json" % name), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(name, "done in %.1f s" % (time.time() - t0), flush=True)
+
+
 def make(name):
+    if name in COMMITTED_CASES:
+        return make_committed(name)
     if name in GENERAL_CASES:
         return make_general(name)
     if name in GOLDILOCKS_CASES:
