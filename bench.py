@@ -507,7 +507,7 @@ def main():
     ap.add_argument("--no-general", action="store_true", help="leave out the general-circuit leg")
     ap.add_argument("--no-goldilocks", action="store_true", help="leave out the Goldilocks-field leg")
     ap.add_argument("--no-committed", action="store_true", help="leave out the committed-input leg")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serving", "copy", "ubench"])
+    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serving", "copy", "ubench", "committed"])
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--jobs", type=int, default=256)
     ap.add_argument("--slots", type=int, default=32)
@@ -545,6 +545,17 @@ def main():
         out["mad_vs_full_rate"] = round(peaks["mad_u64_u32_per_s"] / (VALU_PEAK_TOPS * 1e12), 4)
         out["field_product_macs_per_s"] = round(peaks["field_products_per_s"] * MACS_PER_MULMOD, 1)
         print(json.dumps(out), flush=True)
+        return
+    if args.mode == "committed":
+        peaks = None if args.no_profile else alu_peaks(gkr)
+        res = committed_leg(gkr, args.steps, args.warmup, 0 if args.no_profile else args.profile_steps,
+                            peaks["mad_u64_u32_per_s"] / 1e12 if peaks else None)
+        line = {"metric": "GKR prover with committed inputs: ms per proof", "value": res["field_gates_per_s"],
+                "unit": "field-gates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                "ms_per_step": res["ms_per_proof"], "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": "u32 (BN254 Fr, exact modular integer arithmetic)",
+                "data": "synthetic", "config": {"workload": res["workload"]}, "committed": res}
+        print(json.dumps(line), flush=True)
         return
     if args.mode == "serving":
         res = serving_comparison(gkr, args.jobs, args.slots, args.budget_gib)
