@@ -332,40 +332,160 @@ __global__ void __launch_bounds__(kBlock) k_gl_p1(Step st) {
   }
 }
 
-// ST_GL_P2: phase-2 tables over (y, c) with E[x,c] = EL[x] EC[c]:
-//   M = EC[c] sum_{MUL z: y_z=y} T[z,c] EL[x_z], A likewise over ADD, F = vx M + A, K = vx A.
-// p0 yrow, p1 yent (z, x | type << 31), p2 aU, p3 bV, p4 Cu, p5 Cv, p6 EL, p7 EC, p8 S, p9 F, p10 K,
-// u0 n, q0 count.
-__global__ void __launch_bounds__(kBlock) k_gl_p2(Step st) {
+// ---------------------------------------------------------------- phase 2
+//
+// Phase 2 sums W[y,c] F[y,c] + K[y,c] over (y, c). With the copy weights
+// U[c] = EC[c] Cu[c], V[c] = EC[c] Cv[c] both tables have rank 2 per copy:
+//   F[y,c] = U[c] Fa[y] + V[c] Fb[y],  K[y,c] = U[c] Ka[y] + V[c] Kb[y],
+//   Fa = vx Mu + Au, Fb = vx Mv + Av, Ka = vx Au, Kb = vx Av, where
+//   Mu[y] = sum_{MUL z: y_z = y} aU[z] EL[x_z] (Mv with bV; Au, Av over ADD gates).
+// The sub-circuit rounds therefore run on the 2^sigma tables
+//   sum_y P[y] Fa[y] + Q[y] Fb[y] + Ks[y],  P = sum_c U[c] W[., c], Q = sum_c V[c] W[., c],
+//   Ks = su Ka + sv Kb (su = sum_c U[c], sv = sum_c V[c]),
+// and the copy rounds on Wc[c] = W(ry_local, c), Fc[c] = U[c] Fa~ + V[c] Fb~,
+// Kc[c] = U[c] Ka~ + V[c] Kb~: the same round polynomials as over the whole
+// layer, with two passes over W instead of a pass per round.
+
+// ST_GL_COPY_WEIGHTS (one workgroup): U = EC Cu, V = EC Cv for c < q0, and
+// their sums into S->su, S->sv. p0 EC, p1 Cu, p2 Cv, p3 U, p4 V, p5 S.
+__global__ void __launch_bounds__(kBlock) k_gl_copy_weights(Step st) {
+  const uint64_t *EC = P<const uint64_t*>(st, 0), *Cu = P<const uint64_t*>(st, 1), *Cv = P<const uint64_t*>(st, 2);
+  uint64_t *U = P<uint64_t*>(st, 3), *V = P<uint64_t*>(st, 4);
+  GlState* S = P<GlState*>(st, 5);
+  uint64_t acc[2] = {0, 0};
+  for (uint64_t c = threadIdx.x; c < st.q[0]; c += blockDim.x) {
+    const uint64_t e = gld(EC, c);
+    const uint64_t u = gl_mul(e, gld(Cu, c)), v = gl_mul(e, gld(Cv, c));
+    gst(U, c, u);
+    gst(V, c, v);
+    acc[0] = gl_add(acc[0], u);
+    acc[1] = gl_add(acc[1], v);
+  }
+  gl_block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    S->su = acc[0];
+    S->sv = acc[1];
+  }
+}
+
+// ST_GL_P2T: the 2^sigma phase-2 tables for y < q0 from the wiring by y.
+// p0 yrow, p1 yent (z, x | type << 31), p2 aU, p3 bV, p4 EL, p5 S,
+// p6 Fa, p7 Fb, p8 Ka, p9 Kb, p10 Ks.
+__global__ void __launch_bounds__(kBlock) k_gl_p2t(Step st) {
   const uint32_t* __restrict__ yrow = P<const uint32_t*>(st, 0);
   const uint2* __restrict__ yent = P<const uint2*>(st, 1);
-  const uint64_t *aU = P<const uint64_t*>(st, 2), *bV = P<const uint64_t*>(st, 3);
-  const uint64_t *Cu = P<const uint64_t*>(st, 4), *Cv = P<const uint64_t*>(st, 5);
-  const uint64_t *EL = P<const uint64_t*>(st, 6), *EC = P<const uint64_t*>(st, 7);
-  const uint64_t vx = P<const GlState*>(st, 8)->vx;
-  uint64_t* __restrict__ F = P<uint64_t*>(st, 9);
-  uint64_t* __restrict__ K = P<uint64_t*>(st, 10);
-  const uint32_t n = st.u[0];
-  const uint64_t mask = (1ull << n) - 1;
-  for (uint64_t e = GTID; e < st.q[0]; e += GSTRIDE) {
-    const uint64_t y = e >> n, c = e & mask;
-    const uint64_t cu = gld(Cu, c), cv = gld(Cv, c);
-    uint64_t m = 0, a = 0;
+  const uint64_t *aU = P<const uint64_t*>(st, 2), *bV = P<const uint64_t*>(st, 3), *EL = P<const uint64_t*>(st, 4);
+  const GlState* S = P<const GlState*>(st, 5);
+  const uint64_t vx = S->vx, su = S->su, sv = S->sv;
+  for (uint64_t y = GTID; y < st.q[0]; y += GSTRIDE) {
+    uint64_t mu = 0, mv = 0, au = 0, av = 0;
     const uint32_t k1 = yrow[y + 1];
     for (uint32_t k = yrow[y]; k < k1; ++k) {
       const uint2 r = yent[k];
-      const uint64_t T = gl_add(gl_mul(gld(aU, r.x), cu), gl_mul(gld(bV, r.x), cv));
-      const uint64_t te = gl_mul(T, gld(EL, r.y & 0x7fffffffu));
-      if (r.y >> 31) m = gl_add(m, te);
-      else a = gl_add(a, te);
+      const uint64_t e = gld(EL, r.y & 0x7fffffffu);
+      const uint64_t tu = gl_mul(gld(aU, r.x), e), tv = gl_mul(gld(bV, r.x), e);
+      if (r.y >> 31) {
+        mu = gl_add(mu, tu);
+        mv = gl_add(mv, tv);
+      } else {
+        au = gl_add(au, tu);
+        av = gl_add(av, tv);
+      }
     }
-    const uint64_t ec = gld(EC, c);
-    m = gl_mul(m, ec);
-    a = gl_mul(a, ec);
-    gst(F, e, gl_add(gl_mul(vx, m), a));
-    gst(K, e, gl_mul(vx, a));
+    const uint64_t ka = gl_mul(vx, au), kb = gl_mul(vx, av);
+    gst(P<uint64_t*>(st, 6), y, gl_add(gl_mul(vx, mu), au));
+    gst(P<uint64_t*>(st, 7), y, gl_add(gl_mul(vx, mv), av));
+    gst(P<uint64_t*>(st, 8), y, ka);
+    gst(P<uint64_t*>(st, 9), y, kb);
+    gst(P<uint64_t*>(st, 10), y, gl_add(gl_mul(su, ka), gl_mul(sv, kb)));
   }
 }
+
+// Sum over the wave; valid in every lane.
+__device__ __forceinline__ uint64_t gl_wave_sum(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = gl_add(v, shfl_xor_u64(v, off));
+  return v;
+}
+
+// ST_GL_COPY_CONTRACT: P[y] = sum_c U[c] W[y 2^n + c], Q[y] likewise with V,
+// one wave per row y < q0. p0 W, p1 U, p2 V, p3 P, p4 Q, u0 n.
+__global__ void __launch_bounds__(kBlock) k_gl_copy_contract(Step st) {
+  const uint64_t *W = P<const uint64_t*>(st, 0), *U = P<const uint64_t*>(st, 1), *V = P<const uint64_t*>(st, 2);
+  const uint32_t n = st.u[0];
+  const uint64_t ncop = 1ull << n;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t wave = GTID >> 6, nwaves = GSTRIDE >> 6;
+  for (uint64_t y = wave; y < st.q[0]; y += nwaves) {
+    uint64_t p = 0, q = 0;
+    for (uint64_t c = lane; c < ncop; c += 64) {
+      const uint64_t w = gld(W, (y << n) | c);
+      p = gl_add(p, gl_mul(gld(U, c), w));
+      q = gl_add(q, gl_mul(gld(V, c), w));
+    }
+    p = gl_wave_sum(p);
+    q = gl_wave_sum(q);
+    if (lane == 0) {
+      gst(P<uint64_t*>(st, 3), y, p);
+      gst(P<uint64_t*>(st, 4), y, q);
+    }
+  }
+}
+
+// ST_GL_LOCAL_VALUES (one workgroup): Ka~ = sum_y EqR[y] Ka[y], Kb~ likewise,
+// y < q0, into S->ka_f, S->kb_f. p0 EqR, p1 Ka, p2 Kb, p3 S.
+__global__ void __launch_bounds__(kBlock) k_gl_local_values(Step st) {
+  const uint64_t *E = P<const uint64_t*>(st, 0), *Ka = P<const uint64_t*>(st, 1), *Kb = P<const uint64_t*>(st, 2);
+  GlState* S = P<GlState*>(st, 3);
+  uint64_t acc[2] = {0, 0};
+  for (uint64_t y = threadIdx.x; y < st.q[0]; y += blockDim.x) {
+    const uint64_t e = gld(E, y);
+    acc[0] = gl_add(acc[0], gl_mul(e, gld(Ka, y)));
+    acc[1] = gl_add(acc[1], gl_mul(e, gld(Kb, y)));
+  }
+  gl_block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    S->ka_f = acc[0];
+    S->kb_f = acc[1];
+  }
+}
+
+// ST_GL_LOCAL_CONTRACT: part[ch 2^n + c] = sum over the 2^u1 rows y of chunk
+// ch of EqR[y] W[y 2^n + c], for ch 2^n + c < q0. p0 W, p1 EqR, p2 part, u0 n.
+__global__ void __launch_bounds__(kBlock) k_gl_local_contract(Step st) {
+  const uint64_t *W = P<const uint64_t*>(st, 0), *E = P<const uint64_t*>(st, 1);
+  uint64_t* part = P<uint64_t*>(st, 2);
+  const uint32_t n = st.u[0], lr = st.u[1];
+  const uint64_t mask = (1ull << n) - 1;
+  for (uint64_t g = GTID; g < st.q[0]; g += GSTRIDE) {
+    const uint64_t ch = g >> n, c = g & mask;
+    const uint64_t y0 = ch << lr, y1 = y0 + (1ull << lr);
+    uint64_t acc = 0;
+    for (uint64_t y = y0; y < y1; ++y) acc = gl_add(acc, gl_mul(gld(E, y), gld(W, (y << n) | c)));
+    gst(part, g, acc);
+  }
+}
+
+// ST_GL_COPY_TABLES: for c < q0, Wc[c] = sum of the u0 chunk partials,
+// Fc = U Fa~ + V Fb~, Kc = U Ka~ + V Kb~ (Fa~, Fb~ the first entries of the
+// folded Fa, Fb tables). p0 part, p1 U, p2 V, p3 Fa, p4 Fb, p5 S, p6 Wc, p7 Fc, p8 Kc.
+__global__ void __launch_bounds__(kBlock) k_gl_copy_tables(Step st) {
+  const uint64_t* part = P<const uint64_t*>(st, 0);
+  const uint64_t *U = P<const uint64_t*>(st, 1), *V = P<const uint64_t*>(st, 2);
+  const uint64_t fa = *P<const uint64_t*>(st, 3), fb = *P<const uint64_t*>(st, 4);
+  const GlState* S = P<const GlState*>(st, 5);
+  const uint64_t ka = S->ka_f, kb = S->kb_f, ncop = st.q[0];
+  for (uint64_t c = GTID; c < ncop; c += GSTRIDE) {
+    uint64_t w = 0;
+    for (uint32_t ch = 0; ch < st.u[0]; ++ch) w = gl_add(w, gld(part, (uint64_t)ch * ncop + c));
+    const uint64_t u = gld(U, c), v = gld(V, c);
+    gst(P<uint64_t*>(st, 6), c, w);
+    gst(P<uint64_t*>(st, 7), c, gl_add(gl_mul(u, fa), gl_mul(v, fb)));
+    gst(P<uint64_t*>(st, 8), c, gl_add(gl_mul(u, ka), gl_mul(v, kb)));
+  }
+}
+
+// ---------------------------------------------------------------- rounds
 
 // The transcript step of a round (one thread): message (e0, e1 = claim - e0,
 // e2) to the proof, the hash gives r, the claim moves to the round polynomial at r.
@@ -381,14 +501,23 @@ __device__ __forceinline__ uint64_t gl_round_step(GlState* S, uint64_t e0, uint6
   return r;
 }
 
-// Evaluation of pair b of three tables (W, X, Y) at t = 0 and t = 2, after an
-// optional fold of the source by r (entry i of the folded table is
+// The summand of a round over NT tables at one point: T0 T1 + T2 (NT = 3) or
+// T0 T1 + T2 T3 + T4 (NT = 5).
+template <int NT>
+__device__ __forceinline__ uint64_t gl_form(const uint64_t (&v)[NT]) {
+  if constexpr (NT == 3) return gl_add(gl_mul(v[0], v[1]), v[2]);
+  else return gl_add(gl_add(gl_mul(v[0], v[1]), gl_mul(v[2], v[3])), v[4]);
+}
+
+// Evaluation of pair b of NT tables at t = 0 and t = 2, after an optional
+// fold of the source by r (entry i of the folded table is
 // src[i] + r (src[i + 2 half] - src[i])).
+template <int NT>
 __device__ __forceinline__ void gl_pair(const uint64_t* const* src, uint64_t* const* dst, bool fold, uint64_t r,
                                         uint64_t b, uint64_t half, uint64_t& acc0, uint64_t& acc2) {
-  uint64_t lo[3], hi[3];
+  uint64_t lo[NT], hi[NT];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < NT; ++k) {
     if (fold) {
       const uint64_t m = 2 * half;
       const uint64_t a0 = gld(src[k], b), a1 = gld(src[k], b + m);
@@ -402,28 +531,36 @@ __device__ __forceinline__ void gl_pair(const uint64_t* const* src, uint64_t* co
       hi[k] = gld(src[k], b + half);
     }
   }
-  acc0 = gl_add(acc0, gl_add(gl_mul(lo[0], lo[1]), lo[2]));
-  uint64_t t2[3];
+  acc0 = gl_add(acc0, gl_form<NT>(lo));
+  uint64_t t2[NT];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) t2[k] = gl_sub(gl_double(hi[k]), lo[k]);
-  acc2 = gl_add(acc2, gl_add(gl_mul(t2[0], t2[1]), t2[2]));
+  for (int k = 0; k < NT; ++k) t2[k] = gl_sub(gl_double(hi[k]), lo[k]);
+  acc2 = gl_add(acc2, gl_form<NT>(t2));
 }
 
-// ST_GL_ROUND: one grid-wide round of sum_b W X + Y (optional fold by the
-// previous challenge, evaluation at t = 0, 2), then in the last tile the
-// round's transcript step. p0..2 src, p3..5 dst, p6 rprev (null: no fold),
-// p7 S, p8 partials, p9 r_out, p10 msg, q0 half.
+// ST_GL_ROUND (NT = 3) / ST_GL_ROUND5 (NT = 5): one grid-wide round of the
+// NT-table sum (optional fold by the previous challenge, evaluation at
+// t = 0, 2), then in the last tile the round's transcript step. p0..p(NT-1)
+// src, pNT..p(2NT-1) dst, then (from B = 2 NT) pB rprev (null: no fold),
+// pB+1 S, pB+2 partials, pB+3 r_out, pB+4 msg; q0 half.
+template <int NT>
 __global__ void __launch_bounds__(kBlock) k_gl_round(Step st) {
-  const uint64_t* src[3] = {P<const uint64_t*>(st, 0), P<const uint64_t*>(st, 1), P<const uint64_t*>(st, 2)};
-  uint64_t* dst[3] = {P<uint64_t*>(st, 3), P<uint64_t*>(st, 4), P<uint64_t*>(st, 5)};
-  const uint64_t* rprev = P<const uint64_t*>(st, 6);
-  GlState* S = P<GlState*>(st, 7);
-  uint64_t* partials = P<uint64_t*>(st, 8);
+  constexpr int B = 2 * NT;
+  const uint64_t* src[NT];
+  uint64_t* dst[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    src[k] = P<const uint64_t*>(st, k);
+    dst[k] = P<uint64_t*>(st, NT + k);
+  }
+  const uint64_t* rprev = P<const uint64_t*>(st, B);
+  GlState* S = P<GlState*>(st, B + 1);
+  uint64_t* partials = P<uint64_t*>(st, B + 2);
   const bool fold = rprev != nullptr;
   const uint64_t r = fold ? *rprev : 0;
   const uint64_t half = st.q[0];
   uint64_t acc[2] = {0, 0};
-  for (uint64_t b = GTID; b < half; b += GSTRIDE) gl_pair(src, dst, fold, r, b, half, acc[0], acc[1]);
+  for (uint64_t b = GTID; b < half; b += GSTRIDE) gl_pair<NT>(src, dst, fold, r, b, half, acc[0], acc[1]);
   gl_block_sum<2>(acc);
   if (threadIdx.x == 0) {
     partials[2 * blockIdx.x] = acc[0];
@@ -436,22 +573,30 @@ __global__ void __launch_bounds__(kBlock) k_gl_round(Step st) {
       tot[1] = gl_add(tot[1], partials[2 * b + 1]);
     }
     gl_block_sum<2>(tot);
-    if (threadIdx.x == 0) *P<uint64_t*>(st, 9) = gl_round_step(S, tot[0], tot[1], P<uint64_t*>(st, 10));
+    if (threadIdx.x == 0) *P<uint64_t*>(st, B + 3) = gl_round_step(S, tot[0], tot[1], P<uint64_t*>(st, B + 4));
   }
 }
 
-// ST_GL_TAIL: the remaining u0 rounds in one workgroup, then the final fold;
-// the final value of table 0 goes to *final_out and, when proof_value is not
-// null, to the proof and into the transcript. q0 = table size before the
-// pending fold (if any). p0..2 src, p3..5 dst, p6 rpending, p7 S, p8 r_out,
-// p9 msg, p10 final_out, p11 proof_value.
+// ST_GL_TAIL / ST_GL_TAIL5: the remaining u0 rounds in one workgroup, then
+// the final fold; the final value of table 0 goes to *final_out and, when
+// proof_value is not null, to the proof and into the transcript. q0 = table
+// size before the pending fold (if any). p0..p(NT-1) src, pNT..p(2NT-1) dst,
+// then (from B = 2 NT) pB rpending, pB+1 S, pB+2 r_out, pB+3 msg,
+// pB+4 final_out, pB+5 proof_value.
+template <int NT>
 __global__ void __launch_bounds__(kBlock) k_gl_tail(Step st) {
-  const uint64_t* src[3] = {P<const uint64_t*>(st, 0), P<const uint64_t*>(st, 1), P<const uint64_t*>(st, 2)};
-  uint64_t* dst[3] = {P<uint64_t*>(st, 3), P<uint64_t*>(st, 4), P<uint64_t*>(st, 5)};
-  const uint64_t* rpending = P<const uint64_t*>(st, 6);
-  GlState* S = P<GlState*>(st, 7);
-  uint64_t* r_out = P<uint64_t*>(st, 8);
-  uint64_t* msg = P<uint64_t*>(st, 9);
+  constexpr int B = 2 * NT;
+  const uint64_t* src[NT];
+  uint64_t* dst[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    src[k] = P<const uint64_t*>(st, k);
+    dst[k] = P<uint64_t*>(st, NT + k);
+  }
+  const uint64_t* rpending = P<const uint64_t*>(st, B);
+  GlState* S = P<GlState*>(st, B + 1);
+  uint64_t* r_out = P<uint64_t*>(st, B + 2);
+  uint64_t* msg = P<uint64_t*>(st, B + 3);
   __shared__ uint64_t r_sh;
   bool fold = rpending != nullptr;
   if (threadIdx.x == 0) r_sh = fold ? *rpending : 0;
@@ -461,23 +606,29 @@ __global__ void __launch_bounds__(kBlock) k_gl_tail(Step st) {
     const uint64_t r = r_sh;
     if (fold) {
       const uint64_t m = size / 2;
-      for (uint64_t t = threadIdx.x; t < 3 * m; t += blockDim.x) {
+      for (uint64_t t = threadIdx.x; t < NT * m; t += blockDim.x) {
         const uint32_t k = (uint32_t)(t / m);
         const uint64_t i = t - k * m;
-        const uint64_t* sp = k == 0 ? src[0] : (k == 1 ? src[1] : src[2]);
-        uint64_t* dp = k == 0 ? dst[0] : (k == 1 ? dst[1] : dst[2]);
+        const uint64_t* sp = src[0];
+        uint64_t* dp = dst[0];
+#pragma unroll
+        for (int q = 1; q < NT; ++q)
+          if (k == (uint32_t)q) {
+            sp = src[q];
+            dp = dst[q];
+          }
         const uint64_t a0 = gld(sp, i), a1 = gld(sp, i + m);
         gst(dp, i, gl_add(a0, gl_mul(r, gl_sub(a1, a0))));
       }
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < 3; ++k) src[k] = dst[k];
+      for (int k = 0; k < NT; ++k) src[k] = dst[k];
       size = m;
     }
     if (j == st.u[0]) break;
     const uint64_t half = size / 2;
     uint64_t acc[2] = {0, 0};
-    for (uint64_t b = threadIdx.x; b < half; b += blockDim.x) gl_pair(src, dst, false, 0, b, half, acc[0], acc[1]);
+    for (uint64_t b = threadIdx.x; b < half; b += blockDim.x) gl_pair<NT>(src, dst, false, 0, b, half, acc[0], acc[1]);
     gl_block_sum<2>(acc);
     if (threadIdx.x == 0) {
       const uint64_t rr = gl_round_step(S, acc[0], acc[1], msg + 3 * j);
@@ -489,8 +640,8 @@ __global__ void __launch_bounds__(kBlock) k_gl_tail(Step st) {
   }
   if (threadIdx.x == 0) {
     const uint64_t v = gld(src[0], 0);
-    *P<uint64_t*>(st, 10) = v;
-    uint64_t* proof_value = P<uint64_t*>(st, 11);
+    *P<uint64_t*>(st, B + 4) = v;
+    uint64_t* proof_value = P<uint64_t*>(st, B + 5);
     if (proof_value) {
       *proof_value = v;
       Sha256State sh = gl_load_state(S);
@@ -516,9 +667,16 @@ void launch_gl_step(const Step& st, hipStream_t s) {
     case ST_GL_EQ: k_gl_eq<<<grid, block, 0, s>>>(st); cls = PC_EQ; break;
     case ST_GL_WSUM: k_gl_wsum<<<grid, block, 0, s>>>(st); cls = PC_CLAIM; break;
     case ST_GL_P1: k_gl_p1<<<grid, block, 0, s>>>(st); cls = PC_PHASE1_INIT; break;
-    case ST_GL_P2: k_gl_p2<<<grid, block, 0, s>>>(st); cls = PC_PHASE2_TABLES; break;
-    case ST_GL_ROUND: k_gl_round<<<grid, block, 0, s>>>(st); cls = PC_ROUND_A; break;
-    case ST_GL_TAIL: k_gl_tail<<<grid, block, 0, s>>>(st); cls = PC_TAIL_A; break;
+    case ST_GL_ROUND: k_gl_round<3><<<grid, block, 0, s>>>(st); cls = PC_ROUND_A; break;
+    case ST_GL_TAIL: k_gl_tail<3><<<grid, block, 0, s>>>(st); cls = PC_TAIL_A; break;
+    case ST_GL_ROUND5: k_gl_round<5><<<grid, block, 0, s>>>(st); cls = PC_ROUND_B; break;
+    case ST_GL_TAIL5: k_gl_tail<5><<<grid, block, 0, s>>>(st); cls = PC_TAIL_B; break;
+    case ST_GL_COPY_WEIGHTS: k_gl_copy_weights<<<grid, block, 0, s>>>(st); cls = PC_SMALL; break;
+    case ST_GL_P2T: k_gl_p2t<<<grid, block, 0, s>>>(st); cls = PC_PHASE2_TABLES; break;
+    case ST_GL_COPY_CONTRACT: k_gl_copy_contract<<<grid, block, 0, s>>>(st); cls = PC_COPY_CONTRACT; break;
+    case ST_GL_LOCAL_VALUES: k_gl_local_values<<<grid, block, 0, s>>>(st); cls = PC_SMALL; break;
+    case ST_GL_LOCAL_CONTRACT: k_gl_local_contract<<<grid, block, 0, s>>>(st); cls = PC_LOCAL_CONTRACT; break;
+    case ST_GL_COPY_TABLES: k_gl_copy_tables<<<grid, block, 0, s>>>(st); cls = PC_SMALL; break;
     default: break;
   }
   if (tok >= 0) prof_end(tok, s, cls, st.bytes, st.mulmods);
@@ -551,6 +709,7 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 struct GlWs {
   uint64_t* layer[GKR_MAX_DEPTH + 1];
   uint64_t *G, *H, *Wf, *aU, *bV, *Cu, *Cv, *EL, *EC, *partials, *chal;
+  uint64_t *U, *V, *P, *Q, *Fa, *Fb, *Ka, *Kb, *Ks, *EqR, *Wc, *Fc, *Kc, *wpart;
   uint32_t *dig_a, *dig_b, *dig_in, *dig_out;
   GlState* S;
 };
@@ -567,6 +726,9 @@ GlWs gl_bind(const gkr_circuit& c, void* base, const uint64_t* d_inputs, uint64_
   w.G = U(p.off_G); w.H = U(p.off_H); w.Wf = U(p.off_Wf);
   w.aU = U(p.off_aU); w.bV = U(p.off_bV); w.Cu = U(p.off_Cu); w.Cv = U(p.off_Cv);
   w.EL = U(p.off_EL); w.EC = U(p.off_EC);
+  w.U = U(p.off_U); w.V = U(p.off_V); w.P = U(p.off_P); w.Q = U(p.off_Q); w.Fa = U(p.off_Fa); w.Fb = U(p.off_Fb);
+  w.Ka = U(p.off_Ka); w.Kb = U(p.off_Kb); w.Ks = U(p.off_Ks); w.EqR = U(p.off_EqR); w.Wc = U(p.off_Wc);
+  w.Fc = U(p.off_Fc); w.Kc = U(p.off_Kc); w.wpart = U(p.off_wpart);
   w.partials = U(p.off_partials);
   w.chal = U(p.off_chal);
   w.dig_a = reinterpret_cast<uint32_t*>(b + p.off_dig_a);
@@ -613,42 +775,54 @@ void gl_eq(std::vector<Step>& steps, int count, const uint32_t* bits, const uint
 }
 
 // One phase: grid-wide rounds while the table exceeds 2^tail_log, then the tail.
+// The rounds of one phase over NT tables (3: W X + Y; 5: A B + C D + E):
+// grid-wide rounds while the evaluated table exceeds the tail size, then one
+// workgroup.
+template <int NT>
 void gl_phase(std::vector<Step>& steps, const uint64_t* const* src0, uint64_t* const* dst, uint32_t nrounds,
               GlState* S, uint64_t* partials, uint64_t* r_out, uint64_t* msg, uint64_t* final_out,
               uint64_t* proof_value, const Tuning& tun) {
-  const uint64_t* src[3] = {src0[0], src0[1], src0[2]};
+  constexpr int B = 2 * NT;
+  const uint64_t* src[NT];
+  for (int k = 0; k < NT; ++k) src[k] = src0[k];
   uint64_t eval = 1ull << nrounds;
   uint32_t j = 0;
   const uint64_t* pending = nullptr;
   while (j < nrounds && eval > (1ull << tun.tail_log)) {
     const uint64_t half = eval / 2;
-    Step st = gl_mk(ST_GL_ROUND, gl_tiles(half, tun.max_round_blocks));
-    for (int k = 0; k < 3; ++k) {
+    Step st = gl_mk(NT == 3 ? ST_GL_ROUND : ST_GL_ROUND5, gl_tiles(half, tun.max_round_blocks));
+    for (int k = 0; k < NT; ++k) {
       st.p[k] = src[k];
-      st.p[3 + k] = dst[k];
+      st.p[NT + k] = dst[k];
     }
-    st.p[6] = pending; st.p[7] = S; st.p[8] = partials; st.p[9] = r_out + j; st.p[10] = msg + 3 * j;
+    st.p[B] = pending; st.p[B + 1] = S; st.p[B + 2] = partials; st.p[B + 3] = r_out + j; st.p[B + 4] = msg + 3 * j;
     st.q[0] = half;
-    st.bytes = kGE * 3.0 * (pending ? 6.0 : 2.0) * half;
-    st.mulmods = (pending ? 6.0 : 0.0) * half + 4.0 * half;
+    st.bytes = kGE * NT * (pending ? 6.0 : 2.0) * half;
+    st.mulmods = (pending ? 2.0 * NT : 0.0) * half + (NT == 3 ? 4.0 : 6.0) * half;
     steps.push_back(st);
     if (pending)
-      for (int k = 0; k < 3; ++k) src[k] = dst[k];
+      for (int k = 0; k < NT; ++k) src[k] = dst[k];
     pending = r_out + j;
     ++j;
     eval /= 2;
   }
-  Step st = gl_mk(ST_GL_TAIL, 1);
-  for (int k = 0; k < 3; ++k) {
+  Step st = gl_mk(NT == 3 ? ST_GL_TAIL : ST_GL_TAIL5, 1);
+  for (int k = 0; k < NT; ++k) {
     st.p[k] = src[k];
-    st.p[3 + k] = dst[k];
+    st.p[NT + k] = dst[k];
   }
-  st.p[6] = pending; st.p[7] = S; st.p[8] = r_out + j; st.p[9] = msg + 3 * j; st.p[10] = final_out;
-  st.p[11] = proof_value;
+  st.p[B] = pending; st.p[B + 1] = S; st.p[B + 2] = r_out + j; st.p[B + 3] = msg + 3 * j; st.p[B + 4] = final_out;
+  st.p[B + 5] = proof_value;
   st.q[0] = pending ? 2 * eval : eval;
   st.u[0] = nrounds - j;
-  st.bytes = kGE * 9.0 * eval;
+  st.bytes = kGE * 3.0 * NT * eval;
   steps.push_back(st);
+}
+
+// Row chunks of the local contraction: about 2^18 threads in all.
+uint32_t gl_ychunks(uint32_t sigma, uint32_t n) {
+  const uint64_t want = (n >= 18) ? 1 : (1ull << (18 - n));
+  return (uint32_t)std::min<uint64_t>(want, 1ull << sigma);
 }
 
 uint64_t gl_layer_proof_words(const gkr_circuit& c, uint32_t i) { return 6ull * c.s(i + 1) + 2; }
@@ -728,7 +902,7 @@ void gl_emit_proof(std::vector<Step>& steps, const gkr_circuit& c, const GlWs& w
     {
       const uint64_t* src[3] = {w.layer[i + 1], w.G, w.H};
       uint64_t* dst[3] = {w.Wf, w.G, w.H};
-      gl_phase(steps, src, dst, s1, w.S, w.partials, rx, pr, &w.S->vx, pr + 3 * s1, tun);
+      gl_phase<3>(steps, src, dst, s1, w.S, w.partials, rx, pr, &w.S->vx, pr + 3 * s1, tun);
     }
     {
       const uint32_t bits[2] = {sg1, n};
@@ -737,19 +911,68 @@ void gl_emit_proof(std::vector<Step>& steps, const gkr_circuit& c, const GlWs& w
       uint64_t* outs[2] = {w.EL, w.EC};
       gl_eq(steps, 2, bits, pts, scl, outs);
     }
+    // phase 2 with the copy factors contracted
+    const uint64_t ncop = 1ull << n, rows = 1ull << sg1;
     {
-      Step st = gl_mk(ST_GL_P2, gl_tiles(1ull << s1, kGlSweepTiles));
-      st.p[0] = lw.yrow; st.p[1] = lw.yent; st.p[2] = w.aU; st.p[3] = w.bV; st.p[4] = w.Cu; st.p[5] = w.Cv;
-      st.p[6] = w.EL; st.p[7] = w.EC; st.p[8] = w.S; st.p[9] = w.G; st.p[10] = w.H; st.u[0] = n;
-      st.q[0] = 1ull << s1;
-      st.bytes = kGE * 2.0 * (1ull << s1);
-      st.mulmods = 3.0 * (1ull << c.s(i)) + 4.0 * (1ull << s1);
+      Step st = gl_mk(ST_GL_COPY_WEIGHTS, 1);
+      st.p[0] = w.EC; st.p[1] = w.Cu; st.p[2] = w.Cv; st.p[3] = w.U; st.p[4] = w.V; st.p[5] = w.S; st.q[0] = ncop;
+      st.bytes = kGE * 5.0 * ncop; st.mulmods = 2.0 * ncop;
       steps.push_back(st);
     }
     {
-      const uint64_t* src[3] = {w.layer[i + 1], w.G, w.H};
-      uint64_t* dst[3] = {w.Wf, w.G, w.H};
-      gl_phase(steps, src, dst, s1, w.S, w.partials, ry, pr + 3 * s1 + 1, &w.S->vy, pr + 6 * s1 + 1, tun);
+      Step st = gl_mk(ST_GL_P2T, gl_tiles(rows, kGlSweepTiles));
+      st.p[0] = lw.yrow; st.p[1] = lw.yent; st.p[2] = w.aU; st.p[3] = w.bV; st.p[4] = w.EL; st.p[5] = w.S;
+      st.p[6] = w.Fa; st.p[7] = w.Fb; st.p[8] = w.Ka; st.p[9] = w.Kb; st.p[10] = w.Ks; st.q[0] = rows;
+      st.bytes = kGE * 5.0 * rows; st.mulmods = 2.0 * (double)(1ull << sg) + 6.0 * rows;
+      steps.push_back(st);
+    }
+    {
+      Step st = gl_mk(ST_GL_COPY_CONTRACT, gl_tiles(rows * 64, kGlSweepTiles));
+      st.p[0] = w.layer[i + 1]; st.p[1] = w.U; st.p[2] = w.V; st.p[3] = w.P; st.p[4] = w.Q; st.u[0] = n;
+      st.q[0] = rows;
+      st.bytes = kGE * (double)(rows * ncop); st.mulmods = 2.0 * rows * ncop;
+      steps.push_back(st);
+    }
+    {
+      const uint64_t* src[5] = {w.P, w.Fa, w.Q, w.Fb, w.Ks};
+      uint64_t* dst[5] = {w.P, w.Fa, w.Q, w.Fb, w.Ks};
+      gl_phase<5>(steps, src, dst, sg1, w.S, w.partials, ry, pr + 3 * s1 + 1, &w.S->scratch[1], nullptr, tun);
+    }
+    {
+      const uint32_t bits[1] = {sg1};
+      const uint64_t* pts[1] = {ry};
+      const uint64_t* scl[1] = {nullptr};
+      uint64_t* outs[1] = {w.EqR};
+      gl_eq(steps, 1, bits, pts, scl, outs);
+    }
+    {
+      Step st = gl_mk(ST_GL_LOCAL_VALUES, 1);
+      st.p[0] = w.EqR; st.p[1] = w.Ka; st.p[2] = w.Kb; st.p[3] = w.S; st.q[0] = rows;
+      st.bytes = kGE * 3.0 * rows; st.mulmods = 2.0 * rows;
+      steps.push_back(st);
+    }
+    const uint32_t R = gl_ychunks(sg1, n);
+    {
+      uint32_t lr = 0;
+      while ((1ull << (lr + 1)) * R <= rows) ++lr;  // rows per chunk = rows / R
+      Step st = gl_mk(ST_GL_LOCAL_CONTRACT, gl_tiles((uint64_t)R * ncop, kGlSweepTiles));
+      st.p[0] = w.layer[i + 1]; st.p[1] = w.EqR; st.p[2] = w.wpart; st.u[0] = n; st.u[1] = lr;
+      st.q[0] = (uint64_t)R * ncop;
+      st.bytes = kGE * (double)(rows * ncop + (uint64_t)R * ncop); st.mulmods = (double)(rows * ncop);
+      steps.push_back(st);
+    }
+    {
+      Step st = gl_mk(ST_GL_COPY_TABLES, gl_tiles(ncop, kGlSweepTiles));
+      st.p[0] = w.wpart; st.p[1] = w.U; st.p[2] = w.V; st.p[3] = w.Fa; st.p[4] = w.Fb; st.p[5] = w.S;
+      st.p[6] = w.Wc; st.p[7] = w.Fc; st.p[8] = w.Kc; st.u[0] = R; st.q[0] = ncop;
+      st.bytes = kGE * (double)((uint64_t)R * ncop + 5 * ncop); st.mulmods = 4.0 * ncop;
+      steps.push_back(st);
+    }
+    {
+      const uint64_t* src[3] = {w.Wc, w.Fc, w.Kc};
+      uint64_t* dst[3] = {w.Wc, w.Fc, w.Kc};
+      gl_phase<3>(steps, src, dst, n, w.S, w.partials, ry + sg1, pr + 3 * s1 + 1 + 3 * sg1, &w.S->vy,
+                  pr + 6 * s1 + 1, tun);
     }
     pr += gl_layer_proof_words(c, i);
     chal += 2 * s1;
@@ -787,6 +1010,24 @@ void plan_gl_workspace(gkr_circuit& c) {
   p.off_EL = take(E << sig);
   p.off_EC = take(E << n);
   p.off_partials = take(E * 2 * (size_t)kMaxRoundBlocks);
+  p.off_U = take(E << n);
+  p.off_V = take(E << n);
+  p.off_P = take(E << sig);
+  p.off_Q = take(E << sig);
+  p.off_Fa = take(E << sig);
+  p.off_Fb = take(E << sig);
+  p.off_Ka = take(E << sig);
+  p.off_Kb = take(E << sig);
+  p.off_Ks = take(E << sig);
+  p.off_EqR = take(E << sig);
+  p.off_Wc = take(E << n);
+  p.off_Fc = take(E << n);
+  p.off_Kc = take(E << n);
+  {
+    uint64_t wp = 1;
+    for (uint32_t i = 0; i < d; ++i) wp = std::max<uint64_t>(wp, (uint64_t)gl_ychunks(c.sigma[i + 1], n) << n);
+    p.off_wpart = take(E * wp);
+  }
   const uint64_t big = 1ull << std::max(c.s(0), c.s(d));
   const uint64_t words = (2 * big + kChunkWords - 1) / kChunkWords * 8;
   p.off_dig_a = take(4 * words);

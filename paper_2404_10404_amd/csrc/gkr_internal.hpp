@@ -104,9 +104,16 @@ enum StepType : uint32_t {
   ST_GL_EQ,
   ST_GL_WSUM,
   ST_GL_P1,
-  ST_GL_P2,
   ST_GL_ROUND,
   ST_GL_TAIL,
+  ST_GL_ROUND5,
+  ST_GL_TAIL5,
+  ST_GL_COPY_WEIGHTS,
+  ST_GL_P2T,
+  ST_GL_COPY_CONTRACT,
+  ST_GL_LOCAL_VALUES,
+  ST_GL_LOCAL_CONTRACT,
+  ST_GL_COPY_TABLES,
   ST_GL_END,
   // The commitment to the input layer and its opening: launched by
   // launch_vpd_step, plain path only.
@@ -184,6 +191,8 @@ struct GlState {
   uint32_t counter; // last-workgroup counter of grid reductions (returns to 0)
   uint32_t pad;
   uint64_t claim, alpha, beta, vx, vy;
+  uint64_t su, sv;      // sum_c U[c], sum_c V[c] (phase 2)
+  uint64_t ka_f, kb_f;  // Ka~, Kb~ at the phase-2 local point
   uint64_t scratch[4];  // [0] the output claim V_0~(g)
 };
 
@@ -193,6 +202,9 @@ struct GlPlan {
   size_t off_layer[GKR_MAX_DEPTH + 1];
   size_t off_G, off_H, off_Wf, off_aU, off_bV, off_Cu, off_Cv, off_EL, off_EC, off_partials, off_dig_a,
       off_dig_b, off_dig_in, off_dig_out, off_chal, off_state;
+  // phase 2 with the copy factors contracted
+  size_t off_U, off_V, off_P, off_Q, off_Fa, off_Fb, off_Ka, off_Kb, off_Ks, off_EqR, off_Wc, off_Fc, off_Kc,
+      off_wpart;
 };
 }  // namespace gkr
 
