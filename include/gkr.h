@@ -175,9 +175,10 @@ int32_t gkr_circuit_create_field(uint32_t field, uint32_t depth, uint32_t log_co
 
 /*
  * Whole proof of a Goldilocks circuit (Section 2.2 as for gkr_prove_circuit):
- * d_inputs 2^{s_d} canonical uint64_t (< p), d_outputs receives 2^{s_0}
- * elements, d_proof gkr_proof_bytes() bytes (device, 8-byte aligned). The
- * workspace, stream and error conventions are gkr_prove_circuit's.
+ * d_inputs 2^{s_d} canonical uint64_t (< p; device, 16-byte aligned: the
+ * rounds read it in 16-byte pairs), d_outputs receives 2^{s_0} elements,
+ * d_proof gkr_proof_bytes() bytes (device, 8-byte aligned). The workspace,
+ * stream and error conventions are gkr_prove_circuit's.
  */
 int32_t gkr_gl_prove_circuit(const gkr_circuit* circuit, const uint64_t* d_inputs, uint64_t seed,
                              uint64_t* d_outputs, uint8_t* d_proof, size_t proof_cap, size_t* proof_len,

@@ -36,6 +36,12 @@ typedef __attribute__((address_space(1))) uint64_t GlobalU64;
 __device__ __forceinline__ uint64_t gld(const uint64_t* p, uint64_t i) { return ((const GlobalU64*)p)[i]; }
 __device__ __forceinline__ void gst(uint64_t* p, uint64_t i, uint64_t v) { ((GlobalU64*)p)[i] = v; }
 
+// Two adjacent elements (i even) as one 16-byte access.
+typedef uint64_t U64x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) U64x2 GlobalU64x2;
+__device__ __forceinline__ U64x2 gld2(const uint64_t* p, uint64_t i) { return *(const GlobalU64x2*)(p + i); }
+__device__ __forceinline__ void gst2(uint64_t* p, uint64_t i, U64x2 v) { *(GlobalU64x2*)(p + i) = v; }
+
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
   const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, mask, 64);
   const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), mask, 64);
@@ -538,6 +544,42 @@ __device__ __forceinline__ void gl_pair(const uint64_t* const* src, uint64_t* co
   acc2 = gl_add(acc2, gl_form<NT>(t2));
 }
 
+// Pairs b and b + 1 (b even, half even) of NT tables: gl_pair for both, with
+// 16-byte loads and stores.
+template <int NT>
+__device__ __forceinline__ void gl_pair2(const uint64_t* const* src, uint64_t* const* dst, bool fold, uint64_t r,
+                                         uint64_t b, uint64_t half, uint64_t& acc0, uint64_t& acc2) {
+  uint64_t lo[2][NT], hi[2][NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    if (fold) {
+      const uint64_t m = 2 * half;
+      const U64x2 a0 = gld2(src[k], b), a1 = gld2(src[k], b + m);
+      const U64x2 b0 = gld2(src[k], b + half), b1 = gld2(src[k], b + half + m);
+      lo[0][k] = gl_add(a0.x, gl_mul(r, gl_sub(a1.x, a0.x)));
+      lo[1][k] = gl_add(a0.y, gl_mul(r, gl_sub(a1.y, a0.y)));
+      hi[0][k] = gl_add(b0.x, gl_mul(r, gl_sub(b1.x, b0.x)));
+      hi[1][k] = gl_add(b0.y, gl_mul(r, gl_sub(b1.y, b0.y)));
+      gst2(dst[k], b, U64x2{lo[0][k], lo[1][k]});
+      gst2(dst[k], b + half, U64x2{hi[0][k], hi[1][k]});
+    } else {
+      const U64x2 a = gld2(src[k], b), c = gld2(src[k], b + half);
+      lo[0][k] = a.x;
+      lo[1][k] = a.y;
+      hi[0][k] = c.x;
+      hi[1][k] = c.y;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    acc0 = gl_add(acc0, gl_form<NT>(lo[e]));
+    uint64_t t2[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) t2[k] = gl_sub(gl_double(hi[e][k]), lo[e][k]);
+    acc2 = gl_add(acc2, gl_form<NT>(t2));
+  }
+}
+
 // ST_GL_ROUND (NT = 3) / ST_GL_ROUND5 (NT = 5): one grid-wide round of the
 // NT-table sum (optional fold by the previous challenge, evaluation at
 // t = 0, 2), then in the last tile the round's transcript step. p0..p(NT-1)
@@ -560,7 +602,11 @@ __global__ void __launch_bounds__(kBlock) k_gl_round(Step st) {
   const uint64_t r = fold ? *rprev : 0;
   const uint64_t half = st.q[0];
   uint64_t acc[2] = {0, 0};
-  for (uint64_t b = GTID; b < half; b += GSTRIDE) gl_pair<NT>(src, dst, fold, r, b, half, acc[0], acc[1]);
+  if ((half & 1) == 0) {
+    for (uint64_t b = 2 * GTID; b < half; b += 2 * GSTRIDE) gl_pair2<NT>(src, dst, fold, r, b, half, acc[0], acc[1]);
+  } else {
+    for (uint64_t b = GTID; b < half; b += GSTRIDE) gl_pair<NT>(src, dst, fold, r, b, half, acc[0], acc[1]);
+  }
   gl_block_sum<2>(acc);
   if (threadIdx.x == 0) {
     partials[2 * blockIdx.x] = acc[0];
@@ -790,7 +836,7 @@ void gl_phase(std::vector<Step>& steps, const uint64_t* const* src0, uint64_t* c
   const uint64_t* pending = nullptr;
   while (j < nrounds && eval > (1ull << tun.tail_log)) {
     const uint64_t half = eval / 2;
-    Step st = gl_mk(NT == 3 ? ST_GL_ROUND : ST_GL_ROUND5, gl_tiles(half, tun.max_round_blocks));
+    Step st = gl_mk(NT == 3 ? ST_GL_ROUND : ST_GL_ROUND5, gl_tiles((half + 1) / 2, tun.max_round_blocks));
     for (int k = 0; k < NT; ++k) {
       st.p[k] = src[k];
       st.p[NT + k] = dst[k];
@@ -1060,9 +1106,9 @@ extern "C" int32_t gkr_gl_prove_circuit(const gkr_circuit* c, const uint64_t* d_
     set_error("gkr_gl_prove_circuit takes circuits created for the Goldilocks field");
     return GKR_EINVAL;
   }
-  if ((reinterpret_cast<uintptr_t>(d_inputs) | reinterpret_cast<uintptr_t>(d_outputs) |
-       reinterpret_cast<uintptr_t>(d_proof)) & 7) {
-    set_error("element buffers must be 8-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(d_inputs) & 15) ||
+      ((reinterpret_cast<uintptr_t>(d_outputs) | reinterpret_cast<uintptr_t>(d_proof)) & 7)) {
+    set_error("d_inputs must be 16-byte aligned, d_outputs and d_proof 8-byte aligned");
     return GKR_EINVAL;
   }
   const size_t need = gl_proof_bytes(*c);
