@@ -377,8 +377,8 @@ void Program::local_contract(const Fr* W, const Fr* EqR, Fr* part, uint32_t n, u
 }
 void Program::copy_tables(const Fr* part, uint32_t R, const Fr* U, const Fr* V, const Fr* fa_f, const Fr* fb_f,
                           const DevState* S, Fr* Wc, Fr* Fc, Fr* Kc, uint64_t ncop) {
-  uint32_t tpc_log = 0;
-  while (tpc_log < 8 && (2u << tpc_log) <= R) ++tpc_log;
+  uint32_t tpc_log = 0;  // lanes per column: min(R, 64), as the body computes it
+  while (tpc_log < 6 && (2u << tpc_log) <= R) ++tpc_log;
   const uint64_t cols_per_tile = kBlock >> tpc_log;
   Step st = mk(ST_COPY_TABLES, (uint32_t)std::min<uint64_t>((ncop + cols_per_tile - 1) / cols_per_tile, kSweepTiles));
   st.p[0] = part; st.p[1] = U; st.p[2] = V; st.p[3] = fa_f; st.p[4] = fb_f; st.p[5] = S;
@@ -386,9 +386,10 @@ void Program::copy_tables(const Fr* part, uint32_t R, const Fr* U, const Fr* V, 
   st.bytes = kE * (R + 5.0) * ncop; st.mulmods = 4.0 * ncop;
   steps.push_back(st);
 }
-void Program::local_values(const Fr* EqR, const Fr* Ka, const Fr* Kb, uint64_t rows, DevState* S) {
-  Step st = mk(ST_LOCAL_VALUES, 1);
-  st.p[0] = EqR; st.p[1] = Ka; st.p[2] = Kb; st.p[3] = S; st.q[0] = rows;
+void Program::local_values(const Fr* EqR, const Fr* Ka, const Fr* Kb, uint64_t rows, DevState* S, Fr* partials) {
+  // two rows per thread: a short product chain per thread, then a grid reduction
+  Step st = mk(ST_LOCAL_VALUES, tiles_for((rows + 1) / 2, 64));
+  st.p[0] = EqR; st.p[1] = Ka; st.p[2] = Kb; st.p[3] = S; st.p[4] = partials; st.q[0] = rows;
   st.bytes = 3 * kE * rows; st.mulmods = 2.0 * rows;
   steps.push_back(st);
 }
@@ -492,7 +493,7 @@ void emit_layer(Program& pg, const gkr_circuit& c, uint32_t i, const Workspace& 
     Fr* outs[1] = {w.EqR};
     pg.eq(1, bits, pts, scl, outs);
   }
-  pg.local_values(w.EqR, w.Ka, w.Kb, 1ull << sg1, S);
+  pg.local_values(w.EqR, w.Ka, w.Kb, 1ull << sg1, S, w.partials);
   pg.local_contract(W, w.EqR, w.wpart, n, 1ull << sg1, c.plan.ychunks);
   pg.copy_tables(w.wpart, c.plan.ychunks, w.U, w.V, w.Fa, w.Fb, S, w.Wc, w.Fc, w.Kc, 1ull << n);
   Fr* tc[3] = {w.Wc, w.Fc, w.Kc};

@@ -333,13 +333,21 @@ __device__ __forceinline__ void body_eq(const Step& st, uint32_t tile, uint32_t 
     const Fr* r = P<const Fr*>(st, j);
     const int k = st.u[j];
     const Fr* scale = P<const Fr*>(st, 4 + j);
-    Fr acc = scale ? *scale : fr_one();
-    for (int i = 0; i < k; ++i) {
-      const Fr ri = ldf(r, i);
-      const bool bit = (t >> (k - 1 - i)) & 1;
-      acc = fr_mul(acc, bit ? ri : fr_one_minus(ri));
+    // the k factors in four independent chains (variable i in chain i mod 4),
+    // multiplied together at the end: a dependent chain of about k/4 + 2 products
+    Fr acc[4] = {scale ? *scale : fr_one(), fr_one(), fr_one(), fr_one()};
+    for (int i0 = 0; i0 < k; i0 += 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + q;
+        if (i < k) {
+          const Fr ri = ldf(r, i);
+          const bool bit = (t >> (k - 1 - i)) & 1;
+          acc[q] = fr_mul(acc[q], bit ? ri : fr_one_minus(ri));
+        }
+      }
     }
-    stf(P<Fr*>(st, 8 + j), t, acc);
+    stf(P<Fr*>(st, 8 + j), t, fr_mul(fr_mul(acc[0], acc[1]), fr_mul(acc[2], acc[3])));
   }
 }
 
@@ -941,15 +949,16 @@ __device__ __forceinline__ void body_local_contract(const Step& st, uint32_t til
 }
 
 // ST_COPY_TABLES: the copy tables of phase 2. A column's R partials are summed
-// by tpc = min(256, R) threads:
+// by tpc = min(64, R) lanes of one wave:
 // Wc[c] = sum_k part[c*R + k], Fc[c] = U[c] Fa~ + V[c] Fb~, Kc[c] = U[c] Ka~ + V[c] Kb~.
 // p0 part, p1 U, p2 V, p3 fa_f, p4 fb_f, p5 S, p6 Wc, p7 Fc, p8 Kc, u0 R, q0 ncop.
 __device__ __forceinline__ void body_copy_tables(const Step& st, uint32_t tile, uint32_t ntiles) {
-  __shared__ Fr sw[kBlock];
   const Fr* __restrict__ part = P<const Fr*>(st, 0);
   const uint32_t R = st.u[0];
   const uint64_t ncop = st.q[0];
-  const uint32_t tpc_log = 31 - __clz(R < (uint32_t)kBlock ? R : (uint32_t)kBlock);
+  // tpc lanes (at most a wave) per column, reduced with shuffles inside aligned lane groups
+  const uint32_t rlog = 31 - __clz(R);
+  const uint32_t tpc_log = rlog < 6 ? rlog : 6;
   const uint32_t tpc = 1u << tpc_log;
   const uint32_t lane = threadIdx.x & (tpc - 1);
   const uint64_t cols_per_tile = kBlock >> tpc_log;
@@ -959,16 +968,10 @@ __device__ __forceinline__ void body_copy_tables(const Step& st, uint32_t tile, 
     Fr w = fr_zero();
     if (c < ncop)
       for (uint32_t k = lane; k < R; k += tpc) w = fr_add(w, ldf(part, c * R + k));
-    __syncthreads();
-    sw[threadIdx.x] = w;
-    __syncthreads();
-    for (uint32_t s = tpc / 2; s >= 1; s >>= 1) {
-      if (lane < s) sw[threadIdx.x] = fr_add(sw[threadIdx.x], sw[threadIdx.x + s]);
-      __syncthreads();
-    }
+    for (uint32_t off = tpc / 2; off >= 1; off >>= 1) w = fr_add(w, shfl_xor_fr(w, off));
     if (lane == 0 && c < ncop) {
       const Fr u = ldf(P<const Fr*>(st, 1), c), v = ldf(P<const Fr*>(st, 2), c);
-      stf(P<Fr*>(st, 6), c, sw[threadIdx.x]);
+      stf(P<Fr*>(st, 6), c, w);
       stf(P<Fr*>(st, 7), c, fr_mul_add2(u, *P<const Fr*>(st, 3), v, *P<const Fr*>(st, 4)));
       stf(P<Fr*>(st, 8), c, fr_mul_add2(u, S->ka_f, v, S->kb_f));
     }
@@ -977,17 +980,17 @@ __device__ __forceinline__ void body_copy_tables(const Step& st, uint32_t tile, 
 
 // ST_LOCAL_VALUES: Ka~, Kb~ at the phase-2 sub-circuit point: dot products with
 // EqR (one workgroup). p0 EqR, p1 Ka, p2 Kb, p3 S, q0 rows.
-__device__ __forceinline__ void body_local_values(const Step& st, uint32_t, uint32_t) {
+__device__ __forceinline__ void body_local_values(const Step& st, uint32_t tile, uint32_t ntiles) {
   const Fr* EqR = P<const Fr*>(st, 0);
   const Fr* Ka = P<const Fr*>(st, 1);
   const Fr* Kb = P<const Fr*>(st, 2);
-  DevState* S = P<DevState*>(st, 3);
   Fr acc[2] = {fr_zero(), fr_zero()};
   // lazy sums: at most 16 unreduced products per column accumulator
-  for (uint64_t y0 = threadIdx.x; y0 < st.q[0]; y0 += 16 * kBlock) {
+  const uint64_t stride = (uint64_t)ntiles * kBlock;
+  for (uint64_t y0 = (uint64_t)tile * kBlock + threadIdx.x; y0 < st.q[0]; y0 += 16 * stride) {
     FrCols a = frc_zero(), b = frc_zero();
-    const uint64_t y1 = y0 + 16 * kBlock < st.q[0] ? y0 + 16 * kBlock : st.q[0];
-    for (uint64_t y = y0; y < y1; y += kBlock) {
+    const uint64_t y1 = y0 + 16 * stride < st.q[0] ? y0 + 16 * stride : st.q[0];
+    for (uint64_t y = y0; y < y1; y += stride) {
       const Fr e = ldf(EqR, y);
       frc_mac(a, e, ldf(Ka, y));
       frc_mac(b, e, ldf(Kb, y));
@@ -995,10 +998,15 @@ __device__ __forceinline__ void body_local_values(const Step& st, uint32_t, uint
     acc[0] = fr_add(acc[0], frw_reduce<16>(frc_wide(a)));
     acc[1] = fr_add(acc[1], frw_reduce<16>(frc_wide(b)));
   }
-  block_reduce<2>(acc);
+  write_partial<2>(acc, P<Fr*>(st, 4), tile);
+}
+__device__ __forceinline__ void finish_local_values(const Step& st, uint32_t ntiles) {
+  Fr tot[2];
+  sum_partials<2>(P<const Fr*>(st, 4), ntiles, tot);
   if (threadIdx.x == 0) {
-    S->ka_f = acc[0];
-    S->kb_f = acc[1];
+    DevState* S = P<DevState*>(st, 3);
+    S->ka_f = tot[0];
+    S->kb_f = tot[1];
   }
 }
 
@@ -1040,6 +1048,7 @@ __device__ __forceinline__ void run_step_tile(const Step& st, uint32_t tile, uin
     case ST_P1_INIT_ROUND: counter = &P<DevState*>(st, 9)->counter; break;
     case ST_ROUND_A: counter = &P<DevState*>(st, RoundPtrs<3>::kS)->counter; break;
     case ST_ROUND_B: counter = &P<DevState*>(st, RoundPtrs<5>::kS)->counter; break;
+    case ST_LOCAL_VALUES: counter = &P<DevState*>(st, 3)->counter; break;
     default: break;
   }
   switch (st.type) {
@@ -1075,7 +1084,10 @@ __device__ __forceinline__ void run_step_tile(const Step& st, uint32_t tile, uin
     case ST_COPY_CONTRACT: body_copy_contract(st, tile, ntiles); break;
     case ST_LOCAL_CONTRACT: body_local_contract(st, tile, ntiles); break;
     case ST_COPY_TABLES: body_copy_tables(st, tile, ntiles); break;
-    case ST_LOCAL_VALUES: body_local_values(st, tile, ntiles); break;
+    case ST_LOCAL_VALUES:
+      body_local_values(st, tile, ntiles);
+      if (last_tile(counter, ntiles)) finish_local_values(st, ntiles);
+      break;
     case ST_STATE_EXPORT: body_state_export(st, tile, ntiles); break;
     case ST_STATE_IMPORT: body_state_import(st, tile, ntiles); break;
     default: break;

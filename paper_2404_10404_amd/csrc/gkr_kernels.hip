@@ -39,7 +39,6 @@ GKR_SIMPLE(p2_tables, body_p2_tables)
 GKR_SIMPLE(copy_contract, body_copy_contract)
 GKR_SIMPLE(local_contract, body_local_contract)
 GKR_SIMPLE(copy_tables, body_copy_tables)
-GKR_SIMPLE(local_values, body_local_values)
 GKR_SIMPLE(state_export, body_state_export)
 GKR_SIMPLE(state_import, body_state_import)
 
@@ -54,6 +53,10 @@ __device__ __forceinline__ void run_step_tile_p1_init_round(const Step& st, uint
 __device__ __forceinline__ void run_step_tile_round_a(const Step& st, uint32_t t, uint32_t n) {
   body_round<FormA>(st, t, n);
   if (last_tile(&P<DevState*>(st, RoundPtrs<3>::kS)->counter, n)) finish_round_step<FormA>(st, n);
+}
+__device__ __forceinline__ void run_step_tile_local_values(const Step& st, uint32_t t, uint32_t n) {
+  body_local_values(st, t, n);
+  if (last_tile(&P<DevState*>(st, 3)->counter, n)) finish_local_values(st, n);
 }
 __device__ __forceinline__ void run_step_tile_round_b(const Step& st, uint32_t t, uint32_t n) {
   body_round<FormB>(st, t, n);

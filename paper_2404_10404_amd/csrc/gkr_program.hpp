@@ -42,7 +42,7 @@ struct Program {
   void local_contract(const Fr* W, const Fr* EqR, Fr* part, uint32_t n, uint64_t rows, uint32_t R);
   void copy_tables(const Fr* part, uint32_t R, const Fr* U, const Fr* V, const Fr* fa_f, const Fr* fb_f,
                    const DevState* S, Fr* Wc, Fr* Fc, Fr* Kc, uint64_t ncop);
-  void local_values(const Fr* EqR, const Fr* Ka, const Fr* Kb, uint64_t rows, DevState* S);
+  void local_values(const Fr* EqR, const Fr* Ka, const Fr* Kb, uint64_t rows, DevState* S, Fr* partials);
   void state_export(const DevState* S, uint8_t* out);
   void state_import(DevState* S, const uint8_t* in);
 
