@@ -102,8 +102,10 @@ CLASS_KERNEL = {"round": "k_round_a", "round_sub": "k_round_b", "tail": "k_tail_
                 "g_phase2_tables": "k_g_p2"}
 KERNEL_SOURCES = ["fr.hpp", "sha256.hpp", "gkr_device.hpp", "gkr_kernels.hpp", "gkr_bodies.hpp", "gkr_kernels.hip"]
 # The Goldilocks prover's classes and the sources its kernels are built from.
-GL_CLASS_KERNEL = {"round": "k_gl_round", "tail": "k_gl_tail", "phase1_init": "k_gl_p1",
-                   "phase2_tables": "k_gl_p2", "forward": "k_gl_forward", "digest": "k_gl_digest"}
+GL_CLASS_KERNEL = {"round": "k_gl_round<3>", "round_sub": "k_gl_round<5>", "tail": "k_gl_tail<3>",
+                   "tail_sub": "k_gl_tail<5>", "phase1_init": "k_gl_p1", "phase2_tables": "k_gl_p2t",
+                   "forward": "k_gl_forward", "digest": "k_gl_digest", "copy_contract": "k_gl_copy_contract",
+                   "local_contract": "k_gl_local_contract"}
 GL_KERNEL_SOURCES = ["fr.hpp", "sha256.hpp", "gkr_device.hpp", "gkr_kernels.hpp", "gkr_bodies.hpp", "gl.hpp", "gkr_gl.hip"]
 
 
