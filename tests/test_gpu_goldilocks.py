@@ -53,6 +53,7 @@ SHAPES = [
     (3, 8, (4, 4, 4, 4), 13, (3, 10)),    # many copies
     (2, 1, (11, 3, 12), 14, (1, 1)),      # all MUL
     (2, 2, (5, 6, 4), 15, (0, 1)),        # all ADD
+    (2, 11, (3, 2, 3), 16, (1, 2)),       # 2^11 copies: grid-wide copy rounds in phase 2
 ]
 
 

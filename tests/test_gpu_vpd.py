@@ -204,3 +204,32 @@ def test_committed_worker_share_full_size(gkr):
         x = vpd.point_of_position(2 * idx[j], m, vpd.SHIFT)
         assert f0 == fast.poly_eval_limbs(inputs, x)
         assert f1 == fast.poly_eval_limbs(inputs, (P - x) % P)
+
+
+def test_committed_data_parallel_matches_oracle_golden(gkr):
+    """The committed-input proof of the data-parallel circuit (2^8 copies x
+    depth 16, 2^12 gates/layer: 2^20 inputs, a coset of 2^22, transforms of
+    three passes) with 64 queries, against the oracle's stored root and digests
+    (tests/golden/make_golden.py)."""
+    import hashlib
+    import json
+    import os
+    import torch
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "vpd_c2_proof.json")) as f:
+        gold = json.load(f)
+    spec = gs.data_parallel_c2()
+    assert gold["seed"] == spec.seed and gold["log_copies"] == spec.log_copies and gold["depth"] == spec.depth
+    wiring = gs.make_wiring(spec)
+    c = gkr.Circuit.from_synth(spec, wiring)
+    pr = gkr.CommittedProver(c, gold["queries"])
+    _log("committed c2 golden: proving")
+    pr.prove(gkr.device_elements(gs.make_inputs(spec)), spec.seed)
+    torch.cuda.synchronize()
+    proof = pr.proof_bytes()
+    outs = np.ascontiguousarray(gkr.host_elements(pr.outputs))
+    assert len(proof) == gold["proof_len"]
+    assert proof[:32].hex() == gold["root_hex"]
+    assert hashlib.sha256(outs.tobytes()).hexdigest() == gold["outputs_sha256"]
+    assert hashlib.sha256(proof).hexdigest() == gold["proof_sha256"]
+    _log("committed c2 golden: host verifier")
+    assert gkr.verify_committed(c, outs, spec.seed, proof, gold["queries"]) == 1
