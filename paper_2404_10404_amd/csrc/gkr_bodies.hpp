@@ -806,6 +806,343 @@ __device__ __forceinline__ void body_tail(const Step& st, uint32_t, uint32_t) {
   }
 }
 
+// ---- pipelined tail
+// The round sums of round j + 1 are quadratics in the challenge r_j that folds
+// level j (the tables after j folds) into level j + 1: for pair b of level
+// j + 1 (2Q entries, pairs (b, b + Q)) and point t, each table's value is
+// linear in r_j, equal at r_j = 0 and r_j = 1 to entries of level j (4Q
+// entries): t = 0: L[b] and L[b + 2Q]; t = 2: 2 L[b + Q] - L[b] and
+// 2 L[b + 3Q] - L[b + 2Q]. The term (products of pairs of tables plus the
+// additive table) is then a quadratic q(r) fixed by q(0), q(1) and its leading
+// coefficient (the product of the slopes), three products per task and form
+// product; the sums over tasks give e_t(r) = V0 + r (V1 - V0 - C2) + r^2 C2.
+
+// One task of the coefficient sums: pair b of the next level at t = 0 or 2
+// (t2), from level L (4Q entries); adds q(0), q(1) and the leading coefficient.
+template <class Form>
+__device__ __forceinline__ void tail_task(const Fr* const* L, uint64_t b, uint64_t Q, bool t2, Fr (&acc)[3]) {
+  constexpr int NT = Form::NT;
+  Fr p0[NT], p1[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const Fr a = ldf(L[k], b), c = ldf(L[k], b + 2 * Q);
+    if (t2) {
+      const Fr a1 = ldf(L[k], b + Q), c1 = ldf(L[k], b + 3 * Q);
+      p0[k] = fr_sub(fr_double(a1), a);
+      p1[k] = fr_sub(fr_double(c1), c);
+    } else {
+      p0[k] = a;
+      p1[k] = c;
+    }
+  }
+  Fr v0, v1, c2;
+  if constexpr (NT == 3) {
+    v0 = fr_add(fr_mul(p0[0], p0[1]), p0[2]);
+    v1 = fr_add(fr_mul(p1[0], p1[1]), p1[2]);
+    c2 = fr_mul(fr_sub(p1[0], p0[0]), fr_sub(p1[1], p0[1]));
+  } else {
+    v0 = fr_add(fr_mul_add2(p0[0], p0[1], p0[2], p0[3]), p0[4]);
+    v1 = fr_add(fr_mul_add2(p1[0], p1[1], p1[2], p1[3]), p1[4]);
+    c2 = fr_mul_add2(fr_sub(p1[0], p0[0]), fr_sub(p1[1], p0[1]), fr_sub(p1[2], p0[2]), fr_sub(p1[3], p0[3]));
+  }
+  acc[0] = fr_add(acc[0], v0);
+  acc[1] = fr_add(acc[1], v1);
+  acc[2] = fr_add(acc[2], c2);
+}
+
+// The same for a round whose level needs no fold (the tail's first round when
+// no challenge is pending): pair b of L (2 half entries) at t; a constant
+// quadratic (q(0) = q(1), no leading coefficient).
+template <class Form>
+__device__ __forceinline__ void tail_task_direct(const Fr* const* L, uint64_t b, uint64_t half, bool t2,
+                                                 Fr (&acc)[3]) {
+  constexpr int NT = Form::NT;
+  Fr x[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const Fr lo = ldf(L[k], b);
+    x[k] = t2 ? fr_sub(fr_double(ldf(L[k], b + half)), lo) : lo;
+  }
+  Fr v;
+  if constexpr (NT == 3) v = fr_add(fr_mul(x[0], x[1]), x[2]);
+  else v = fr_add(fr_mul_add2(x[0], x[1], x[2], x[3]), x[4]);
+  acc[0] = fr_add(acc[0], v);
+  acc[1] = fr_add(acc[1], v);
+}
+
+// Worker waves whose tasks are nonempty for `tasks` tasks per half.
+__device__ __forceinline__ uint32_t tail_active_waves(uint64_t tasks, uint32_t hw) {
+  const uint64_t w = (tasks + 63) / 64;
+  return w < hw ? (uint32_t)w : hw;
+}
+
+// The coefficient sums of one point over one half of the worker waves: each
+// thread takes tasks th, th + nth, ..; each wave with tasks sums its lanes and
+// stores (V0, V1, C2) in part[wave of the half].
+template <class Form>
+__device__ __forceinline__ void tail_coefficients(const Fr* const* L, uint64_t tasks, bool direct, bool t2,
+                                                  uint32_t th, uint32_t nth, uint32_t wih, uint32_t nact,
+                                                  Fr (*part)[3]) {
+  if (wih >= nact) return;  // the wave has no task
+  Fr acc[3] = {fr_zero(), fr_zero(), fr_zero()};
+  if (direct) {
+    for (uint64_t b = th; b < tasks; b += nth) tail_task_direct<Form>(L, b, tasks, t2, acc);
+  } else {
+    for (uint64_t b = th; b < tasks; b += nth) tail_task<Form>(L, b, tasks, t2, acc);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) acc[k] = wave_sum_to_lane63(acc[k]);
+  if ((threadIdx.x & 63) == 63) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) part[wih][k] = acc[k];
+  }
+}
+
+// Round j + 1's coefficient sums for at most 32 pairs: coefficient s (q(0),
+// q(1) or the leading one) of every task in one wave, lanes 0..31 at t = 0 and
+// lanes 32..63 at t = 2, one pair per lane (one product, or one pair of
+// products for Form B); a segmented sum leaves the totals in lanes 31 and 63.
+template <class Form>
+__device__ __forceinline__ void tail_coefficient_stream(const Fr* const* L, uint64_t Q, uint32_t s,
+                                                        Fr (*part)[8][3]) {
+  constexpr int NT = Form::NT;
+  const uint32_t lane = threadIdx.x & 63;
+  const bool t2 = lane >= 32;
+  const uint64_t b = lane & 31;
+  Fr v = fr_zero();
+  if (b < Q) {
+    Fr p[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      if (s == 2 && k == NT - 1) {  // the additive table has no slope product
+        p[k] = fr_zero();
+        continue;
+      }
+      Fr x0 = fr_zero(), x1 = fr_zero();
+      if (s != 1) {
+        const Fr a = ldf(L[k], b);
+        x0 = t2 ? fr_sub(fr_double(ldf(L[k], b + Q)), a) : a;
+      }
+      if (s != 0) {
+        const Fr c = ldf(L[k], b + 2 * Q);
+        x1 = t2 ? fr_sub(fr_double(ldf(L[k], b + 3 * Q)), c) : c;
+      }
+      p[k] = s == 0 ? x0 : (s == 1 ? x1 : fr_sub(x1, x0));
+    }
+    if constexpr (NT == 3) v = fr_add(fr_mul(p[0], p[1]), p[2]);
+    else v = fr_add(fr_mul_add2(p[0], p[1], p[2], p[3]), p[4]);
+  }
+  v = fr_add(v, dpp_fr<0xB1, 0xF>(v));   // quad_perm [1,0,3,2]
+  v = fr_add(v, dpp_fr<0x4E, 0xF>(v));   // quad_perm [2,3,0,1]
+  v = fr_add(v, dpp_fr<0x141, 0xF>(v));  // row_half_mirror
+  v = fr_add(v, dpp_fr<0x140, 0xF>(v));  // row_mirror
+  v = fr_add(v, dpp_fr<0x142, 0xA>(v));  // row_bcast15 into rows 1 and 3
+  if (lane == 31) part[0][0][s] = v;
+  if (lane == 63) part[1][0][s] = v;
+}
+
+// The claim through a round with sums e0, e2 (e1 = claim - e0) and challenge
+// r: g(r) = e0 + r (A + r B) with B = (e2 - 2 e1 + e0) / 2, A = e1 - e0 - B.
+__device__ __forceinline__ Fr tail_claim_next(const Fr& claim, const Fr& e0, const Fr& e2, const Fr& r) {
+  const Fr e1 = fr_sub(claim, e0);
+  const Fr B = fr_half(fr_add(fr_sub(e2, fr_double(e1)), e0));
+  const Fr A = fr_sub(fr_sub(e1, e0), B);
+  return fr_add(e0, fr_mul(r, fr_add(A, fr_mul(r, B))));
+}
+
+// A round's message (e0, e1 = claim - e0, e2 in canonical form), lane k
+// converting and storing element k.
+__device__ __forceinline__ void tail_message(const Fr& claim, const Fr& e0, const Fr& e2, uint32_t* msg) {
+  const uint32_t lane = threadIdx.x & 63;
+  const Fr e1 = fr_sub(claim, e0);
+  Fr x = e0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x.v[k] = lane == 1 ? e1.v[k] : (lane == 2 ? e2.v[k] : x.v[k]);
+  const Fr c = fr_from_mont(x);
+  if (lane < 3) stf(reinterpret_cast<Fr*>(msg), lane, c);
+}
+
+// ST_TAIL_A / ST_TAIL_B, pipelined: the same rounds, messages, challenges and
+// final values as body_tail, with the table work off the hash chain. Eight
+// waves (two per SIMD, wave w on SIMD w mod 4), by role:
+//  - wave 0 holds the transcript: in round j it sums the workers' coefficient
+//    partials of round j, evaluates them at r_{j-1} (two products) and hashes
+//    (e0, e2) into r_j;
+//  - in the first half of round j, wave 1 moves the claim through round
+//    j - 1 (two products) and wave 7 writes round j - 1's message (e0, e1 =
+//    claim - e0, e2 in canonical form) from the claim before it;
+//  - waves 2-7 fold level j - 1 into level j by r_{j-1} (first half of round
+//    j, before a workgroup barrier); then, while wave 0 hashes, waves 1-7
+//    compute round j + 1's coefficients from level j: for more than 32
+//    pairs, one task (three products) per thread; for at most 32, one product
+//    per lane, waves 2, 3 and 5 taking q(0), q(1) and the leading coefficient.
+// Two workgroup barriers per round; the previous round's values sit in
+// alternating shared slots.
+template <class Form>
+__device__ __forceinline__ void body_tail_pipe(const Step& st, uint32_t, uint32_t) {
+  constexpr int NT = Form::NT;
+  const Fr* src[NT];
+  Fr* dst[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    src[k] = P<const Fr*>(st, k);
+    dst[k] = P<Fr*>(st, NT + k);
+  }
+  const Fr* rpending = P<const Fr*>(st, 2 * NT);
+  DevState* S = P<DevState*>(st, 2 * NT + 1);
+  Fr* r_out = P<Fr*>(st, 2 * NT + 2);
+  uint32_t* msg = P<uint32_t*>(st, 2 * NT + 3);
+  Fr* final_out = P<Fr*>(st, 2 * NT + 4);
+  uint32_t* proof_value = P<uint32_t*>(st, 2 * NT + 5);
+  const uint32_t wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // Per-thread coefficient tasks: waves 2, 3, 1 at t = 0 and 5, 6, 7, 4 at
+  // t = 2 (the first waves of each group on different SIMDs, for few tasks).
+  // Folds: waves 2, 3, 5, 6, 4, 7 in that order. Wave 4 shares SIMD 0 with
+  // wave 0 and wave 5 SIMD 1 with wave 1: the older wave of a SIMD issues
+  // first, so the transcript, claim and message chains keep their speed.
+  constexpr uint32_t kHw0 = 3, kHw2 = 4;  // coefficient waves for t = 0 and t = 2
+  const bool worker = wid != 0;
+  const bool t2 = wid >= 4;
+  const uint32_t wih = t2 ? (wid == 4 ? 3 : wid - 5) : (wid == 1 ? 2 : wid - 2);  // index in its group
+  const uint32_t th = wih * 64 + lane, nth = (t2 ? kHw2 : kHw0) * 64;
+  const uint32_t ford = wid == 4 ? 4 : (wid == 7 ? 5 : wid - 2 - (wid > 4));
+  const uint32_t fw = ford * 64 + lane, nfw = 6 * 64;  // index among the folders
+  const uint64_t size = st.q[0];
+  const uint32_t rounds = st.u[0];
+  const bool pending = rpending != nullptr;
+  __shared__ Fr part[2][8][3];    // coefficient partials (half, wave, V0 V1 C2)
+  __shared__ Fr r_sh[2], e_sh[2][2], claim_sh[2];
+  // Values that cross a barrier live in the shared slots (r_sh, e_sh) rather
+  // than in registers: every wave holds the registers of every role.
+  Sha256State state;  // wave 0
+  Fr claim;           // waves 1 and 7: the claim before the first round (wave 1 moves it)
+  bool grid_pend = false;  // waves 1 and 7: a grid round whose claim move is pending
+  if (wid == 0) {
+    state = load_state(S);
+    if (lane == 0) r_sh[1] = pending ? ldf(rpending, 0) : fr_zero();  // r_{-1}
+  } else if (wid == 1 || wid == 7) {
+    claim = S->claim;
+    grid_pend = S->pending != 0;
+  }
+  const Fr* cur[NT];  // the current level
+#pragma unroll
+  for (int k = 0; k < NT; ++k) cur[k] = src[k];
+  // round 0's coefficients: from the unfolded tables (a pending fold) or directly
+  uint64_t tasks = 0;
+  if (rounds > 0) tasks = pending ? size / 4 : size / 2;
+  uint32_t nact0 = tail_active_waves(tasks, kHw0), nact2 = tail_active_waves(tasks, kHw2);
+  if (worker && rounds > 0)
+    tail_coefficients<Form>(cur, tasks, !pending, t2, th, nth, wih, t2 ? nact2 : nact0, part[t2 ? 1 : 0]);
+  __syncthreads();
+  for (uint32_t j = 0; j < rounds; ++j) {
+    const bool fold = pending || j > 0;
+    const uint64_t m = 1ull << (rounds - j);  // entries of level j
+    if (wid == 0) {
+      // round j's sums at r_{j-1}: lane 0 for t = 0, lane 1 for t = 2
+      const uint32_t h = lane & 1, nact = h ? nact2 : nact0;
+      const Fr r_prev = opaque(r_sh[(j - 1) & 1]);
+      Fr v0 = fr_zero(), v1 = fr_zero(), c2 = fr_zero();
+      for (uint32_t a = 0; a < nact; ++a) {
+        v0 = fr_add(v0, part[h][a][0]);
+        v1 = fr_add(v1, part[h][a][1]);
+        c2 = fr_add(c2, part[h][a][2]);
+      }
+      const Fr c1 = fr_sub(fr_sub(v1, v0), c2);
+      const Fr e = fr_add(v0, fr_mul(r_prev, fr_add(c1, fr_mul(r_prev, c2))));
+      if (lane < 2) e_sh[j & 1][lane] = e;
+    } else if (wid == 1) {
+      // the claim through round j - 1 (or the pending grid round)
+      if (j > 0) {
+        const uint32_t q = (j - 1) & 1;
+        claim = tail_claim_next(claim, opaque(e_sh[q][0]), opaque(e_sh[q][1]), opaque(r_sh[q]));
+      }
+      else if (grid_pend) claim = tail_claim_next(claim, opaque(S->pend_e0), opaque(S->pend_e2), opaque(S->pend_r));
+      if (lane == 0) claim_sh[j & 1] = claim;
+    } else {  // waves 2-7: the folders
+      if (wid == 7) {
+        // round j - 1's message (or the pending grid round's), from the claim before it
+        if (j > 0) {
+          const uint32_t q = (j - 1) & 1;
+          tail_message(opaque(claim_sh[q]), opaque(e_sh[q][0]), opaque(e_sh[q][1]), msg + 24 * (j - 1));
+        } else if (grid_pend) {
+          tail_message(claim, opaque(S->pend_e0), opaque(S->pend_e2), S->pend_msg);
+        }
+      }
+      if (fold) {
+        // level j - 1 into level j by r_{j-1} (in place after the first fold)
+        const Fr rf = opaque(r_sh[(j - 1) & 1]);
+        const uint32_t lg = rounds - j;
+        for (uint64_t t = fw; t < NT * m; t += nfw) {
+          const uint32_t k = (uint32_t)(t >> lg);
+          const uint64_t i = t & (m - 1);
+          const Fr* sp = pick<NT>(cur, k);
+          const Fr a0 = ldf(sp, i), a1 = ldf(sp, i + m);
+          stf(pick<NT>(dst, k), i, fr_add(a0, fr_mul(rf, fr_sub(a1, a0))));
+        }
+      }
+    }
+    if (fold) {
+#pragma unroll
+      for (int k = 0; k < NT; ++k) cur[k] = dst[k];
+    }
+    __syncthreads();
+    const uint64_t next = j + 1 < rounds ? m / 4 : 0;  // tasks of round j + 1
+    if (wid == 0) {
+      const Fr r = round_hash_wave(state, opaque(e_sh[j & 1][0]), opaque(e_sh[j & 1][1]));
+      if (lane == 0) {
+        r_sh[j & 1] = r;
+        stf(r_out, j, r);
+      }
+    } else if (next > 32) {
+      if (worker)
+        tail_coefficients<Form>(cur, next, false, t2, th, nth, wih,
+                                t2 ? tail_active_waves(next, kHw2) : tail_active_waves(next, kHw0), part[t2 ? 1 : 0]);
+    } else if (next && (wid == 2 || wid == 3 || wid == 5)) {
+      tail_coefficient_stream<Form>(cur, next, wid == 2 ? 0 : (wid == 3 ? 1 : 2), part);
+    }
+    nact0 = next > 32 ? tail_active_waves(next, kHw0) : 1;
+    nact2 = next > 32 ? tail_active_waves(next, kHw2) : 1;
+    __syncthreads();
+  }
+  // the final fold (by r_{rounds-1}, or by the pending challenge when no
+  // round is left) and the last claim move
+  const bool any_fold = pending || rounds > 0;
+  if (wid == 0) {
+    const Fr r_prev = opaque(r_sh[(rounds - 1) & 1]);  // r_{rounds-1}, or r_{-1}
+    Fr v = fr_zero();  // lane k: the final value of table k
+    if (any_fold && lane < NT) {
+      const Fr* sp = pick<NT>(cur, lane);
+      const Fr a0 = ldf(sp, 0), a1 = ldf(sp, 1);
+      v = fr_add(a0, fr_mul(r_prev, fr_sub(a1, a0)));
+      stf(pick<NT>(dst, lane), 0, v);
+    }
+    if (lane == 0) {
+      if (rounds > 0) save_state(S, state);
+      if (!any_fold) v = ldf(src[0], 0);
+      if (proof_value) finish_value(S, v, final_out, proof_value);
+      else *final_out = v;
+    }
+  } else if (wid == 1) {
+    if (rounds > 0) {
+      const uint32_t q = (rounds - 1) & 1;
+      claim = tail_claim_next(claim, opaque(e_sh[q][0]), opaque(e_sh[q][1]), opaque(r_sh[q]));
+    } else if (grid_pend) {
+      claim = tail_claim_next(claim, opaque(S->pend_e0), opaque(S->pend_e2), opaque(S->pend_r));
+    }
+    if (lane == 0) {
+      S->claim = claim;
+      S->pending = 0;
+    }
+  } else if (wid == 7) {
+    if (rounds > 0) {
+      const uint32_t q = (rounds - 1) & 1;
+      tail_message(opaque(claim_sh[q]), opaque(e_sh[q][0]), opaque(e_sh[q][1]), msg + 24 * (rounds - 1));
+    } else if (grid_pend) {
+      tail_message(claim, opaque(S->pend_e0), opaque(S->pend_e2), S->pend_msg);
+    }
+  }
+}
+
 // ST_COPY_WEIGHTS: U[c] = Cu[c] EC[c], V[c] = Cv[c] EC[c]; SU, SV their sums
 // (one workgroup). p0 Cu, p1 Cv, p2 EC, p3 U, p4 V, p5 S, q0 ncop.
 __device__ __forceinline__ void body_copy_weights(const Step& st, uint32_t, uint32_t) {
@@ -963,6 +1300,8 @@ __device__ __forceinline__ void body_copy_tables(const Step& st, uint32_t tile, 
   const uint32_t lane = threadIdx.x & (tpc - 1);
   const uint64_t cols_per_tile = kBlock >> tpc_log;
   const DevState* S = P<const DevState*>(st, 5);
+  const Fr fa = opaque(*P<const Fr*>(st, 3)), fb = opaque(*P<const Fr*>(st, 4));
+  const Fr ka = opaque(S->ka_f), kb = opaque(S->kb_f);
   for (uint64_t base = (uint64_t)tile * cols_per_tile; base < ncop; base += (uint64_t)ntiles * cols_per_tile) {
     const uint64_t c = base + (threadIdx.x >> tpc_log);
     Fr w = fr_zero();
@@ -972,8 +1311,8 @@ __device__ __forceinline__ void body_copy_tables(const Step& st, uint32_t tile, 
     if (lane == 0 && c < ncop) {
       const Fr u = ldf(P<const Fr*>(st, 1), c), v = ldf(P<const Fr*>(st, 2), c);
       stf(P<Fr*>(st, 6), c, w);
-      stf(P<Fr*>(st, 7), c, fr_mul_add2(u, *P<const Fr*>(st, 3), v, *P<const Fr*>(st, 4)));
-      stf(P<Fr*>(st, 8), c, fr_mul_add2(u, S->ka_f, v, S->kb_f));
+      stf(P<Fr*>(st, 7), c, fr_mul_add2(u, fa, v, fb));
+      stf(P<Fr*>(st, 8), c, fr_mul_add2(u, ka, v, kb));
     }
   }
 }

@@ -85,6 +85,15 @@ __device__ __forceinline__ void acquire_agent_wait() {
   wait_vmem();
 }
 
+// A value in registers the compiler cannot trace back to its load: a kernel
+// that never writes a field may otherwise load it again at every use (in the
+// middle of a product's chain of multiply-adds) instead of keeping it live.
+__device__ __forceinline__ Fr opaque(Fr x) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) asm volatile("" : "+v"(x.v[k]));
+  return x;
+}
+
 template <class T>
 __device__ __forceinline__ T P(const Step& st, int i) {
   return reinterpret_cast<T>(const_cast<void*>(st.p[i]));

@@ -189,7 +189,7 @@ __device__ __forceinline__ void body_g_layer_begin(const Step& st, uint32_t, uin
   for (uint32_t k = 0; k < K; ++k) {
     const Fr a = st.u[1] ? fr_one() : squeeze(sh);
     stf(coef, k, a);
-    claim = fr_add(claim, fr_mul(a, *P<const Fr*>(st, 2 + k)));
+    claim = fr_add(claim, fr_mul(a, opaque(*P<const Fr*>(st, 2 + k))));
   }
   if (!st.u[1]) save_state(S, sh);
   S->claim = claim;

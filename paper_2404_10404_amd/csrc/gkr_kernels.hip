@@ -32,8 +32,8 @@ GKR_SIMPLE(squeeze, body_squeeze)
 GKR_SIMPLE(layer_begin, body_layer_begin)
 GKR_SIMPLE(eq, body_eq)
 GKR_SIMPLE(p1_init, body_p1_init)
-GKR_SIMPLE(tail_a, body_tail<FormA>)
-GKR_SIMPLE(tail_b, body_tail<FormB>)
+GKR_SIMPLE(tail_a, body_tail_pipe<FormA>)
+GKR_SIMPLE(tail_b, body_tail_pipe<FormB>)
 GKR_SIMPLE(copy_weights, body_copy_weights)
 GKR_SIMPLE(p2_tables, body_p2_tables)
 GKR_SIMPLE(copy_contract, body_copy_contract)

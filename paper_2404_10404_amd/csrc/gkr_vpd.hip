@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(kNttThreads) k_vpd_ntt(Step st) {
   const Fr sc = words_fr(st.w);
   for (uint32_t e = threadIdx.x; e < nelem; e += kNttThreads) {
     const uint32_t r = e >> c, col = e & (C - 1);
-    const Fr v = do_scale ? fr_mul(tile[e], sc) : tile[e];
+    const Fr v = do_scale ? fr_mul(opaque(tile[e]), sc) : tile[e];
     stf(x, base + ((uint64_t)r << lo) + col, v);
   }
 }
@@ -506,8 +506,8 @@ __global__ void __launch_bounds__(kBlock) k_vpd_fold0(Step st) {
   const Fr *wlo = P<const Fr*>(st, 5), *whi = P<const Fr*>(st, 6);
   const Fr *wilo = P<const Fr*>(st, 7), *wihi = P<const Fr*>(st, 8);
   const Fr gam = words_fr(st.w), ginv2 = words_fr(st.w + 8);
-  const Fr a0 = V->a[0], a1 = V->a[1], a2 = V->a[2], a3 = V->a[3];
-  const Fr cb = fr_mul(V->beta[0], ginv2);
+  const Fr a0 = opaque(V->a[0]), a1 = opaque(V->a[1]), a2 = opaque(V->a[2]), a3 = opaque(V->a[3]);
+  const Fr cb = opaque(fr_mul(opaque(V->beta[0]), ginv2));
   for (uint64_t u = GTID; u < st.q[0]; u += GSTRIDE) {
     const uint64_t k = bitrev_bits((uint32_t)u, st.u[0]);
     const Fr x = fr_mul(gam, pow2lvl(wlo, whi, k));
@@ -530,7 +530,7 @@ __global__ void __launch_bounds__(kBlock) k_vpd_fold(Step st) {
   const VpdState* V = P<const VpdState*>(st, 2);
   const Fr *wilo = P<const Fr*>(st, 3), *wihi = P<const Fr*>(st, 4);
   const uint32_t i = st.u[1];
-  const Fr cb = fr_mul(V->beta[i], words_fr(st.w));
+  const Fr cb = opaque(fr_mul(opaque(V->beta[i]), words_fr(st.w)));
   for (uint64_t u = GTID; u < st.q[0]; u += GSTRIDE) {
     const uint64_t k = bitrev_bits((uint32_t)u, st.u[0]);
     const Fr a = ldf(in, 2 * u), b = ldf(in, 2 * u + 1);
@@ -548,7 +548,7 @@ __global__ void k_vpd_final(Step st) {
   DevState* S = P<DevState*>(st, 1);
   uint32_t* proof = P<uint32_t*>(st, 2);
   VpdState* V = P<VpdState*>(st, 3);
-  const Fr c = fr_from_mont(last[0]);
+  const Fr c = fr_from_mont(opaque(last[0]));
   Sha256State sh = load_state(S);
   absorb_element(sh, kTagValue, c);
 #pragma unroll
