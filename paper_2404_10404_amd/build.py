@@ -15,7 +15,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgkr.so")
 SOURCES = ["gkr_batch_kernel.hip", "gkr_kernels.hip", "gkr_api.hip", "gkr_tuning.cpp", "gkr_verify.cpp",
            "gkr_profile.cpp", "gkr_batch.hip", "gkr_ubench.hip", "gkr_noalloc.hip", "gkr_general.hip", "gkr_gl.hip",
-           "gkr_vpd.hip"]
+           "gkr_vpd.hip", "gkr_contract.hip"]
 # Test helper: the device field-code checker the GPU tests load.
 ROOT = os.path.dirname(HERE)
 CHECKER_SRC = os.path.join(ROOT, "tests", "native", "fr_device_check.hip")

@@ -12,6 +12,7 @@
 #include "gkr_gl.hpp"
 #include "gkr_kernels.hpp"
 #include "gkr_program.hpp"
+#include "gkr_contract.hpp"
 #include "gkr_tuning.hpp"
 #include "gkr_vpd.hpp"
 
@@ -121,6 +122,9 @@ size_t plan_workspace(const gkr_circuit& c, Plan& p) {
   p.off_dig_out = take(32);
   p.off_chal = take(E * ((size_t)c.s(0) + 2ull * d * sp_max + 2ull * s_max + 8));
   p.off_state = take(sizeof(DevState));
+  p.cc_bytes = 0;
+  for (uint32_t i = 0; i < d; ++i) p.cc_bytes = std::max(p.cc_bytes, cc_scratch_bytes(n, c.sigma[i + 1]));
+  p.off_cc = take(p.cc_bytes);
   p.total = off;
   return off;
 }
@@ -165,6 +169,7 @@ Workspace bind_workspace(const gkr_circuit& c, void* base) {
   w.dig_out = reinterpret_cast<uint32_t*>(b + p.off_dig_out);
   w.chal = F(p.off_chal);
   w.state = reinterpret_cast<DevState*>(b + p.off_state);
+  w.cc = p.cc_bytes ? static_cast<void*>(b + p.off_cc) : nullptr;
   w.bytes = p.total;
   return w;
 }
@@ -406,7 +411,8 @@ void Program::state_import(DevState* S, const uint8_t* in) {
 
 void Program::run(hipStream_t s) const {
   for (const Step& st : steps) {
-    if (st.type >= ST_VPD_POWERS) launch_vpd_step(st, s);
+    if (st.type >= ST_CC_BUILD) launch_cc_step(st, s);
+    else if (st.type >= ST_VPD_POWERS) launch_vpd_step(st, s);
     else if (st.type >= ST_GL_FORWARD) launch_gl_step(st, s);
     else if (st.type >= ST_G_GATHER) launch_general_step(st, s);
     else launch_step(st, s);
@@ -482,7 +488,8 @@ void emit_layer(Program& pg, const gkr_circuit& c, uint32_t i, const Workspace& 
   }
   pg.copy_weights(w.Cu, w.Cv, w.EC, w.U, w.V, 1ull << n, S);
   pg.p2_tables(c.wiring[i], w.aU, w.bV, w.EL, S, w.Fa, w.Fb, w.Ka, w.Kb, w.Ks, 1ull << sg1, 1ull << sg);
-  pg.copy_contract(W, w.U, w.V, w.P, w.Q, n, 1ull << sg1);
+  if (pg.matrix_cores && w.cc && cc_applies(n, sg1)) emit_copy_contract_mfma(pg, W, w.U, w.V, w.P, w.Q, n, sg1, w.cc);
+  else pg.copy_contract(W, w.U, w.V, w.P, w.Q, n, 1ull << sg1);
   Fr* tb[5] = {w.P, w.Fa, w.Q, w.Fb, w.Ks};
   const Fr* tb_src[5] = {w.P, w.Fa, w.Q, w.Fb, w.Ks};
   emit_phase<5>(pg, tb_src, tb, sg1, S, w.partials, ry, proof + off_p2, &S->scratch[1], nullptr, tun);

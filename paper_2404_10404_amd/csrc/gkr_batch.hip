@@ -60,6 +60,7 @@ int32_t gkr_plan_create(const gkr_job* job, gkr_plan** out) {
   try {
     Workspace w = bind_workspace(*c, job->d_ws);
     Program pg;
+    pg.matrix_cores = false;
     emit_prove_circuit(pg, *c, w, job->d_inputs, job->seed, job->d_outputs, job->d_proof, current_tuning());
     gkr_plan* p = new gkr_plan();
     p->job = *job;

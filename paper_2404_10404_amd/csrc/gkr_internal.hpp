@@ -132,7 +132,13 @@ enum StepType : uint32_t {
   ST_VPD_FOLD,
   ST_VPD_FINAL,
   ST_VPD_QUERIES,
-  ST_VPD_END
+  ST_VPD_END,
+  // The copy contraction on the matrix cores: launched by launch_cc_step,
+  // plain path only.
+  ST_CC_BUILD = 192,
+  ST_CC_BSUM,
+  ST_CC_GEMM,
+  ST_CC_EPILOGUE
 };
 
 struct Step {
@@ -161,6 +167,7 @@ struct Workspace {
   Fr *P, *Q, *Fa, *Fb, *Ks, *Ka, *Kb;
   Fr *Wc, *Fc, *Kc, *wpart;
   Fr* partials;
+  void* cc;                 // matrix-core contraction scratch (null if no layer uses it)
   uint32_t *dig_a, *dig_b;  // tree-digest levels (8 words per digest)
   uint32_t* dig_in;         // final digests (8 words each)
   uint32_t* dig_out;
@@ -174,7 +181,8 @@ struct Plan {
   size_t off_layer[GKR_MAX_DEPTH + 1];
   size_t off_G, off_H, off_Wf, off_aU, off_bV, off_Cu, off_Cv, off_U, off_V, off_EC, off_EL,
       off_EqR, off_P, off_Q, off_Fa, off_Fb, off_Ks, off_Ka, off_Kb, off_Wc, off_Fc, off_Kc,
-      off_wpart, off_partials, off_dig_a, off_dig_b, off_dig_in, off_dig_out, off_chal, off_state;
+      off_wpart, off_partials, off_dig_a, off_dig_b, off_dig_in, off_dig_out, off_chal, off_state, off_cc;
+  size_t cc_bytes;
   size_t total;
   uint32_t ychunks;  // y-range split of the phase-2 copy-table pass
   size_t dig_level_words;

@@ -12,6 +12,9 @@ namespace gkr {
 
 struct Program {
   std::vector<Step> steps;
+  // Steps that only the plain launcher runs (the matrix-core contraction) are
+  // allowed; the batch kernel's programs switch this off.
+  bool matrix_cores = true;
 
   void to_mont(const gkr_fr* in, Fr* out, uint64_t n);
   void from_mont(const Fr* in, gkr_fr* out, uint64_t n);

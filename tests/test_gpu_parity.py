@@ -4,7 +4,8 @@ Field arithmetic is exact, so the bar is bit-exactness: the whole proof, the
 outputs and every intermediate value handed back through the C ABI must equal
 the oracle's bytes. Shapes cover several tiles and the single-workgroup tail
 (tables above and below 2^10 entries), ragged layer widths, a single copy,
-zero-width layers and the multi-workgroup sub-circuit rounds of phase 2.
+zero-width layers, the multi-workgroup sub-circuit rounds of phase 2 and
+the matrix-core copy contraction (2^10 copies, at least 2^8 wires).
 """
 import sys
 
@@ -56,6 +57,8 @@ SHAPES = [
     (3, 8, (4, 4, 4, 4), 13, (3, 10)),        # many copies: grid-wide copy rounds
     (2, 1, (11, 3, 12), 14, (1, 1)),          # all MUL, mismatched widths
     (2, 2, (5, 6, 4), 15, (0, 1)),            # all ADD
+    (2, 10, (8, 8, 8), 16, (1, 2)),           # 2^10 copies: matrix-core copy contraction, one K block per chunk
+    (2, 10, (7, 8, 9), 17, (3, 10)),          # ragged widths: one, then two row tiles
 ]
 
 
