@@ -96,7 +96,7 @@ def profile_pass(gkr, prover, d_in, seed, steps):
 
 # Profile class -> kernel, for the traffic records taken with rocprofv3 --pmc.
 CLASS_KERNEL = {"round": "k_round_a", "round_sub": "k_round_b", "tail": "k_tail_a", "tail_sub": "k_tail_b",
-                "phase1_init": "k_p1_init_round", "forward": "k_forward", "copy_contract": "k_copy_contract",
+                "phase1_init": "k_p1_init_round", "forward": "k_forward", "copy_contract": "k_cc_gemm",
                 "local_contract": "k_local_contract", "digest": "k_digest", "g_gather": "k_g_gather",
                 "g_forward": "k_g_forward", "g_claim_tables": "k_g_ttable", "g_phase1_init": "k_g_p1",
                 "g_phase2_tables": "k_g_p2"}
