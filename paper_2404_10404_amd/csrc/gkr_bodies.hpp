@@ -431,6 +431,15 @@ __device__ __forceinline__ void body_p1_init_round(const Step& st, uint32_t tile
   Fr acc[2] = {fr_zero(), fr_zero()};
   FrWide e0 = frw_zero();
   uint32_t lazy = 0;
+  // Lazy: the running sums wait in shared memory (a slot per thread), out of
+  // the registers the gate walks need
+  __shared__ Fr sacc[Lazy ? 2 : 1][Lazy ? kBlock : 1];
+  __shared__ FrWide swide[Lazy ? kBlock : 1];
+  if constexpr (Lazy) {
+    sacc[0][threadIdx.x] = fr_zero();
+    sacc[1][threadIdx.x] = fr_zero();
+    swide[threadIdx.x] = frw_zero();
+  }
   for (uint64_t b = GTID; b < half; b += GSTRIDE) {
     Fr g0, h0, g1, h1;
     phase1_entry(st, b, g0, h0);
@@ -446,16 +455,23 @@ __device__ __forceinline__ void body_p1_init_round(const Step& st, uint32_t tile
       acc[1] = fr_add(acc[1], fr_add(fr_mul(w2, g2), h2));
       continue;
     }
-    frw_mac(e0, w0, g0);
-    acc[0] = fr_add(acc[0], h0);
-    acc[1] = fr_add(acc[1], fr_add(fr_mul(w2, g2), h2));
+    FrWide ew = swide[threadIdx.x];
+    frw_mac(ew, w0, g0);
+    Fr a0 = fr_add(sacc[0][threadIdx.x], h0);
+    sacc[1][threadIdx.x] = fr_add(sacc[1][threadIdx.x], fr_add(fr_mul(w2, g2), h2));
     if (++lazy == 16) {
-      acc[0] = fr_add(acc[0], frw_reduce<16>(e0));
-      e0 = frw_zero();
+      a0 = fr_add(a0, frw_reduce<16>(ew));
+      ew = frw_zero();
       lazy = 0;
     }
+    swide[threadIdx.x] = ew;
+    sacc[0][threadIdx.x] = a0;
   }
-  if (lazy) acc[0] = fr_add(acc[0], frw_reduce<16>(e0));
+  if constexpr (Lazy) {
+    acc[0] = sacc[0][threadIdx.x];
+    acc[1] = sacc[1][threadIdx.x];
+    if (lazy) acc[0] = fr_add(acc[0], frw_reduce<16>(swide[threadIdx.x]));
+  }
   write_partial<2>(acc, P<Fr*>(st, 10), tile);
 }
 

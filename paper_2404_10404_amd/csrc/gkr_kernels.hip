@@ -73,7 +73,11 @@ GKR_PLAIN_KERNEL(k_layer_begin, layer_begin)
 GKR_PLAIN_KERNEL(k_eq, eq)
 GKR_PLAIN_KERNEL(k_wsum, wsum)
 GKR_PLAIN_KERNEL(k_p1_init, p1_init)
-GKR_PLAIN_KERNEL_OCC3(k_p1_init_round, p1_init_round)
+#define GKR_PLAIN_KERNEL_OCC4(NAME, TYPE)                                         \
+  __global__ void __launch_bounds__(kBlock, 4) NAME(Step st) {                    \
+    run_step_tile_##TYPE(st, blockIdx.x, gridDim.x);                              \
+  }
+GKR_PLAIN_KERNEL_OCC4(k_p1_init_round, p1_init_round)
 GKR_PLAIN_KERNEL_OCC3(k_round_a, round_a)
 GKR_PLAIN_KERNEL_OCC3(k_round_b, round_b)
 // The single-workgroup tails run with kTailBlock threads (two waves per SIMD).
