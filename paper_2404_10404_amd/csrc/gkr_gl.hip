@@ -475,19 +475,36 @@ __global__ void __launch_bounds__(kBlock) k_gl_local_contract(Step st) {
 // ST_GL_COPY_TABLES: for c < q0, Wc[c] = sum of the u0 chunk partials,
 // Fc = U Fa~ + V Fb~, Kc = U Ka~ + V Kb~ (Fa~, Fb~ the first entries of the
 // folded Fa, Fb tables). p0 part, p1 U, p2 V, p3 Fa, p4 Fb, p5 S, p6 Wc, p7 Fc, p8 Kc.
+// tpc lanes (up to a wave) per column, summed with shuffles inside aligned
+// lane groups: few copies come with many chunks.
 __global__ void __launch_bounds__(kBlock) k_gl_copy_tables(Step st) {
   const uint64_t* part = P<const uint64_t*>(st, 0);
   const uint64_t *U = P<const uint64_t*>(st, 1), *V = P<const uint64_t*>(st, 2);
   const uint64_t fa = *P<const uint64_t*>(st, 3), fb = *P<const uint64_t*>(st, 4);
   const GlState* S = P<const GlState*>(st, 5);
   const uint64_t ka = S->ka_f, kb = S->kb_f, ncop = st.q[0];
-  for (uint64_t c = GTID; c < ncop; c += GSTRIDE) {
+  const uint32_t R = st.u[0];
+  const uint32_t rlog = 31 - __clz(R);
+  const uint32_t tpc_log = rlog < 6 ? rlog : 6;
+  const uint32_t tpc = 1u << tpc_log, lane = threadIdx.x & (tpc - 1);
+  const uint64_t cols_per_tile = kBlock >> tpc_log;
+  const uint32_t tile = blockIdx.x, ntiles = gridDim.x;
+  for (uint64_t base = (uint64_t)tile * cols_per_tile; base < ncop; base += (uint64_t)ntiles * cols_per_tile) {
+    const uint64_t c = base + (threadIdx.x >> tpc_log);
     uint64_t w = 0;
-    for (uint32_t ch = 0; ch < st.u[0]; ++ch) w = gl_add(w, gld(part, (uint64_t)ch * ncop + c));
-    const uint64_t u = gld(U, c), v = gld(V, c);
-    gst(P<uint64_t*>(st, 6), c, w);
-    gst(P<uint64_t*>(st, 7), c, gl_add(gl_mul(u, fa), gl_mul(v, fb)));
-    gst(P<uint64_t*>(st, 8), c, gl_add(gl_mul(u, ka), gl_mul(v, kb)));
+    if (c < ncop)
+      for (uint32_t ch = lane; ch < R; ch += tpc) w = gl_add(w, gld(part, (uint64_t)ch * ncop + c));
+    for (uint32_t off = tpc / 2; off >= 1; off >>= 1) {
+      const uint64_t o = ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(w >> 32), off, 64) << 32) |
+                         (uint32_t)__shfl_xor((int)(uint32_t)w, off, 64);
+      w = gl_add(w, o);
+    }
+    if (lane == 0 && c < ncop) {
+      const uint64_t u = gld(U, c), v = gld(V, c);
+      gst(P<uint64_t*>(st, 6), c, w);
+      gst(P<uint64_t*>(st, 7), c, gl_add(gl_mul(u, fa), gl_mul(v, fb)));
+      gst(P<uint64_t*>(st, 8), c, gl_add(gl_mul(u, ka), gl_mul(v, kb)));
+    }
   }
 }
 
@@ -1008,7 +1025,9 @@ void gl_emit_proof(std::vector<Step>& steps, const gkr_circuit& c, const GlWs& w
       steps.push_back(st);
     }
     {
-      Step st = gl_mk(ST_GL_COPY_TABLES, gl_tiles(ncop, kGlSweepTiles));
+      uint32_t tl = 0;
+      while ((1u << (tl + 1)) <= R && tl < 6) ++tl;  // lanes per column, as in the kernel
+      Step st = gl_mk(ST_GL_COPY_TABLES, gl_tiles(ncop << tl, kGlSweepTiles));
       st.p[0] = w.wpart; st.p[1] = w.U; st.p[2] = w.V; st.p[3] = w.Fa; st.p[4] = w.Fb; st.p[5] = w.S;
       st.p[6] = w.Wc; st.p[7] = w.Fc; st.p[8] = w.Kc; st.u[0] = R; st.q[0] = ncop;
       st.bytes = kGE * (double)((uint64_t)R * ncop + 5 * ncop); st.mulmods = 4.0 * ncop;
