@@ -173,6 +173,27 @@ def roofline(prof, workload=None, mac_peak_tops=None, macs_per_mulmod=MACS_PER_M
     return r
 
 
+def class_fractions(prof, mac_peak_tops, product_rate=None, macs_per_mulmod=MACS_PER_MULMOD, top=6):
+    """Per kernel class (the longest ones): time, launches and the fractions of
+    the HBM peak, of the measured v_mad_u64_u32 rate (products x multiply-adds
+    per product) and, when given, of the measured whole field-product rate
+    (gkr_ubench kind 4: the product runs at its multiply-add-with-carry pair
+    rate, below the bare multiply-add rate)."""
+    out = {}
+    for name, e in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:top]:
+        sec = e["ms"] / 1e3
+        if sec <= 0:
+            continue
+        d = {"ms": round(e["ms"], 3), "launches": e["launches"],
+             "hbm_frac": round(e["bytes"] / sec / 1e9 / HBM_PEAK_GBS, 4)}
+        if e["mulmods"] and mac_peak_tops:
+            d["alu_frac"] = round(e["mulmods"] * macs_per_mulmod / sec / 1e12 / mac_peak_tops, 4)
+        if e["mulmods"] and product_rate:
+            d["product_frac"] = round(e["mulmods"] / sec / product_rate, 4)
+        out[name] = d
+    return out
+
+
 def cpu_baseline(spec, budget_s=20.0):
     """The oracle (pure Python, one core) on a slice of the workload with fewer
     copies; its rate carries over to the whole workload (the prover is linear
@@ -629,6 +650,8 @@ def main():
         log("%s: profile pass (HIP events per launch)" % args.workload)
         prof = profile_pass(gkr, prover, d_in, spec.seed, args.profile_steps)
         line["roofline"] = roofline(prof, args.workload, peaks["mad_u64_u32_per_s"] / 1e12)
+        line["kernel_classes"] = class_fractions(prof, peaks["mad_u64_u32_per_s"] / 1e12,
+                                                 peaks.get("field_products_per_s"))
         line["kernels"] = {k: {"ms": round(v["ms"], 4), "launches": v["launches"]} for k, v in
                            sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
         line["alu_peaks_measured"] = {k: round(v, 1) for k, v in peaks.items()}
