@@ -287,7 +287,7 @@ void Program::p1_init(const Fr* W, Fr* G, Fr* H, const LayerWiring& lw, const Fr
   Step st = mk(ST_P1_INIT, tiles_for(count, kSweepTiles));
   p1_common(st, W, G, H, lw, aU, bV, Cu, Cv, n);
   st.q[0] = count;
-  st.bytes = kE * (gates + 2.0 * count); st.mulmods = 3.0 * gates;
+  st.bytes = kE * (gates + 2.0 * count); st.mulmods = 2.5 * gates;  // T (1.5) and T W (1) per gate
   steps.push_back(st);
 }
 void Program::p1_init_round(const Fr* W, Fr* G, Fr* H, const LayerWiring& lw, const Fr* aU,
@@ -300,13 +300,16 @@ void Program::p1_init_round(const Fr* W, Fr* G, Fr* H, const LayerWiring& lw, co
   p1_common(st, W, G, H, lw, aU, bV, Cu, Cv, n);
   st.q[0] = half;
   st.p[9] = S; st.p[10] = partials; st.p[11] = r_out; st.p[12] = msg;
-  st.bytes = kE * (gates + 6.0 * half); st.mulmods = 3.0 * gates + 2.0 * half;
+  st.bytes = kE * (gates + 6.0 * half); st.mulmods = 2.5 * gates + 1.5 * half;  // + lazy w0 g0, product w2 g2
   steps.push_back(st);
 }
 
 // Algorithmic bytes and products of one round over `half` pairs of NT tables
 // (eval_products products per evaluation point).
-static void round_work(int nt, int eval_products, uint64_t half, bool fold, double& bytes, double& mm) {
+// Work of a step in product equivalents: a full Montgomery product is one, an
+// unreduced 8x8-limb product and a reduction are a half each (a*b + c*d with
+// one reduction is 1.5).
+static void round_work(int nt, double eval_products, uint64_t half, bool fold, double& bytes, double& mm) {
   const double h = (double)half;
   bytes += fold ? kE * nt * 6.0 * h : kE * nt * 2.0 * h;
   mm += (fold ? 2.0 * nt * h : 0.0) + eval_products * 2.0 * h;
@@ -324,7 +327,7 @@ void Program::round(const Fr* const* src, Fr* const* dst, uint64_t half, const F
   }
   st.p[R::kR] = rprev; st.p[R::kS] = S; st.p[R::kPart] = partials; st.p[R::kROut] = r_out; st.p[R::kMsg] = msg;
   st.q[0] = half;
-  round_work(NT, NT == 3 ? 1 : 2, half, rprev != nullptr, st.bytes, st.mulmods);
+  round_work(NT, NT == 3 ? 1.0 : 1.5, half, rprev != nullptr, st.bytes, st.mulmods);
   steps.push_back(st);
 }
 template <int NT>
@@ -342,7 +345,7 @@ void Program::tail(const Fr* const* src, Fr* const* dst, uint64_t size, const Fr
   uint64_t sz = size;
   for (uint32_t j = 0; j < rounds; ++j) {
     const uint64_t ev = fold ? sz / 2 : sz;
-    round_work(NT, NT == 3 ? 1 : 2, ev / 2, fold, st.bytes, st.mulmods);
+    round_work(NT, NT == 3 ? 1.0 : 1.5, ev / 2, fold, st.bytes, st.mulmods);
     fold = true;
     sz = ev;
   }
@@ -369,7 +372,7 @@ void Program::copy_contract(const Fr* W, const Fr* U, const Fr* V, Fr* Pt, Fr* Q
   Step st = mk(ST_COPY_CONTRACT, (uint32_t)std::min<uint64_t>((rows + rows_per_tile - 1) / rows_per_tile, kSweepTiles));
   st.p[0] = W; st.p[1] = U; st.p[2] = V; st.p[3] = Pt; st.p[4] = Qt; st.u[0] = n; st.q[0] = rows;
   const double elems = (double)(rows << n);
-  st.bytes = kE * elems; st.mulmods = 2.0 * elems;
+  st.bytes = kE * elems; st.mulmods = elems;  // two unreduced products per entry
   steps.push_back(st);
 }
 void Program::local_contract(const Fr* W, const Fr* EqR, Fr* part, uint32_t n, uint64_t rows, uint32_t R) {
@@ -377,7 +380,7 @@ void Program::local_contract(const Fr* W, const Fr* EqR, Fr* part, uint32_t n, u
   Step st = mk(ST_LOCAL_CONTRACT, (uint32_t)std::min<uint64_t>(xb * R, kSweepTiles));
   st.p[0] = W; st.p[1] = EqR; st.p[2] = part; st.u[0] = n; st.u[1] = R; st.q[0] = rows;
   const double elems = (double)(rows << n);
-  st.bytes = kE * elems; st.mulmods = elems;
+  st.bytes = kE * elems; st.mulmods = 0.5 * elems;  // one unreduced product per entry
   steps.push_back(st);
 }
 void Program::copy_tables(const Fr* part, uint32_t R, const Fr* U, const Fr* V, const Fr* fa_f, const Fr* fb_f,
@@ -388,7 +391,7 @@ void Program::copy_tables(const Fr* part, uint32_t R, const Fr* U, const Fr* V, 
   Step st = mk(ST_COPY_TABLES, (uint32_t)std::min<uint64_t>((ncop + cols_per_tile - 1) / cols_per_tile, kSweepTiles));
   st.p[0] = part; st.p[1] = U; st.p[2] = V; st.p[3] = fa_f; st.p[4] = fb_f; st.p[5] = S;
   st.p[6] = Wc; st.p[7] = Fc; st.p[8] = Kc; st.u[0] = R; st.q[0] = ncop;
-  st.bytes = kE * (R + 5.0) * ncop; st.mulmods = 4.0 * ncop;
+  st.bytes = kE * (R + 5.0) * ncop; st.mulmods = 3.0 * ncop;
   steps.push_back(st);
 }
 void Program::local_values(const Fr* EqR, const Fr* Ka, const Fr* Kb, uint64_t rows, DevState* S, Fr* partials) {

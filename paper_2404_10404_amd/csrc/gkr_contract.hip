@@ -324,8 +324,7 @@ void emit_copy_contract_mfma(Program& pg, const Fr* W, const Fr* U, const Fr* V,
     Step st = mk(ST_CC_GEMM, cp.row_tiles * cp.chunks);
     st.p[0] = W; st.p[1] = Bt; st.p[2] = part; st.u[0] = n; st.u[1] = cp.row_tiles;
     st.q[0] = cp.chunk_bytes; st.q[1] = rows;
-    st.bytes = 32.0 * (double)(rows << n) + (double)cp.part_bytes;
-    st.mulmods = 2.0 * (double)(rows << n);
+    st.bytes = 32.0 * (double)(rows << n) + (double)cp.part_bytes;  // no field products: int8 matrix work
     pg.steps.push_back(st);
   }
   {
@@ -333,6 +332,7 @@ void emit_copy_contract_mfma(Program& pg, const Fr* W, const Fr* U, const Fr* V,
     st.p[0] = part; st.p[1] = BS; st.p[2] = Pt; st.p[3] = Qt; st.u[0] = cp.chunks; st.q[0] = rows;
     two_pow_508(st.w);
     st.bytes = (double)cp.part_bytes + 64.0 * rows;
+    st.mulmods = (double)rows;  // one reduction per row and vector
     pg.steps.push_back(st);
   }
 }
