@@ -386,6 +386,18 @@ int32_t gkr_set_tuning(uint32_t tail_log, uint32_t max_round_blocks, uint32_t pa
 int32_t gkr_get_tuning(uint32_t* tail_log, uint32_t* max_round_blocks, uint32_t* pairs_per_thread);
 
 /*
+ * How plain proofs contract phase 2's copy factors (process-wide; this
+ * library's own, no passage; proof bytes never depend on it): 1 (the
+ * default) runs the contraction on the int8 matrix cores for layers with at
+ * least 2^10 copies and 2^8 sub-circuit wires, 0 always runs the scalar
+ * lazy-product pass. Proofs read it when they are queued. Errors: GKR_EINVAL
+ * for a mode above 1 (nothing is changed). gkr_get_contraction writes the
+ * current mode to a non-null pointer.
+ */
+int32_t gkr_set_contraction(uint32_t matrix_cores);
+int32_t gkr_get_contraction(uint32_t* matrix_cores);
+
+/*
  * Kernel timing for measurement (this library's own, no passage). While enabled, every launch is bracketed by
  * two HIP events on its own stream (do not enable it while capturing a HIP
  * graph). gkr_profile_read waits for the recorded events and returns, per

@@ -491,7 +491,7 @@ void emit_layer(Program& pg, const gkr_circuit& c, uint32_t i, const Workspace& 
   }
   pg.copy_weights(w.Cu, w.Cv, w.EC, w.U, w.V, 1ull << n, S);
   pg.p2_tables(c.wiring[i], w.aU, w.bV, w.EL, S, w.Fa, w.Fb, w.Ka, w.Kb, w.Ks, 1ull << sg1, 1ull << sg);
-  if (pg.matrix_cores && w.cc && cc_applies(n, sg1)) emit_copy_contract_mfma(pg, W, w.U, w.V, w.P, w.Q, n, sg1, w.cc);
+  if (pg.matrix_cores && tun.matrix_cores && w.cc && cc_applies(n, sg1)) emit_copy_contract_mfma(pg, W, w.U, w.V, w.P, w.Q, n, sg1, w.cc);
   else pg.copy_contract(W, w.U, w.V, w.P, w.Q, n, 1ull << sg1);
   Fr* tb[5] = {w.P, w.Fa, w.Q, w.Fb, w.Ks};
   const Fr* tb_src[5] = {w.P, w.Fa, w.Q, w.Fb, w.Ks};

@@ -157,6 +157,7 @@ struct Tuning {
   uint32_t tail_log;          // single-workgroup tail once a table has <= 2^tail_log entries
   uint32_t max_round_blocks;  // cap on the workgroups of a grid-wide round
   uint32_t pairs_per_thread;  // a grid-wide round gives each thread at least this many pairs
+  uint32_t matrix_cores;      // 1: the phase-2 copy contraction on the int8 matrix cores where it applies
 };
 
 // Device buffers of one proof, carved out of the caller's workspace.

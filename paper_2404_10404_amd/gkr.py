@@ -489,6 +489,8 @@ def _batch_lib():
         L.gkr_set_tuning.argtypes = [_u32, _u32, _u32]
         L.gkr_set_tuning.restype = _i32
         L.gkr_get_tuning.argtypes = [ctypes.POINTER(_u32), ctypes.POINTER(_u32), ctypes.POINTER(_u32)]
+        L.gkr_set_contraction.argtypes = [_u32]
+        L.gkr_set_contraction.restype = _i32
         L.gkr_get_tuning.restype = _i32
         L._batch_ready = True
     return L
@@ -549,6 +551,12 @@ def prove_batch(jobs: Sequence[Job], stream=None):
 
 def set_tuning(tail_log: int, max_round_blocks: int, pairs_per_thread: int = 1):
     _check(_batch_lib().gkr_set_tuning(tail_log, max_round_blocks, pairs_per_thread))
+
+
+def set_contraction(matrix_cores: bool):
+    """Phase-2 copy contraction of plain proofs: on the int8 matrix cores where
+    a layer qualifies (True, the default) or always the scalar pass."""
+    _check(_batch_lib().gkr_set_contraction(1 if matrix_cores else 0))
 
 
 UBENCH_KINDS = {0: "v_mad_u64_u32", 1: "v_mad_u64_u32 + v_addc (field multiply-accumulate)",

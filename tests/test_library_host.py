@@ -120,6 +120,21 @@ def test_tuning_round_trip_and_ranges():
         gkr.set_tuning(*old)
 
 
+def test_contraction_mode_round_trip_and_range():
+    import ctypes
+    L = gkr._batch_lib()
+    mode = ctypes.c_uint32(7)
+    assert L.gkr_get_contraction(ctypes.byref(mode)) == 0 and mode.value == 1
+    try:
+        gkr.set_contraction(False)
+        assert L.gkr_get_contraction(ctypes.byref(mode)) == 0 and mode.value == 0
+        assert L.gkr_set_contraction(2) != 0
+        assert L.gkr_get_contraction(ctypes.byref(mode)) == 0 and mode.value == 0
+    finally:
+        gkr.set_contraction(True)
+    assert L.gkr_get_contraction(ctypes.byref(mode)) == 0 and mode.value == 1
+
+
 def test_build_refuses_register_spills():
     """The build reads the compiler's resource-usage remarks and refuses a
     kernel that spills vector registers to scratch memory."""
