@@ -38,9 +38,10 @@ import numpy as np  # noqa: E402
 import gkr_synth as gs  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# Full-rate 32-bit VALU issue (theoretical): 256 CUs x 4 SIMDs x 16 lanes x
-# 2.4 GHz. The roofline uses the measured v_mad_u64_u32 rate instead.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Full-rate 32-bit VALU issue (theoretical): 256 CUs x 4 SIMDs x 32 lanes x
+# 2.4 GHz (the 157.3 TFLOP/s fp32 vector rate counted as single operations).
+# The roofline uses the measured v_mad_u64_u32 rate instead.
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 # 32x32 multiply-accumulates of one schoolbook Montgomery product with 8 limbs
 # (64 for the product, 64 + 8 for the reduction).
 MACS_PER_MULMOD = 2 * 8 * 8 + 8
@@ -58,6 +59,8 @@ def alu_peaks(gkr):
                       (3, "mul_u32_per_s"), (4, "field_products_per_s")):
         rate, ms = gkr.ubench(kind, 1024 if kind < 4 else 64)
         out[key] = rate
+    # the HBM stream of a folding round without its arithmetic (8 passes of 3 GiB)
+    out["round_stream_bytes_per_s"] = gkr.ubench(5, 8)[0]
     return out
 
 WORKLOADS = {
@@ -140,12 +143,14 @@ def traffic_record(kernel, workload, sources=None):
 
 
 def roofline(prof, workload=None, mac_peak_tops=None, macs_per_mulmod=MACS_PER_MULMOD, class_kernel=None,
-             sources=None):
+             sources=None, stream_gbs=None):
     """Roofline of the dominant kernel class: t_roof = max(bytes / HBM peak,
     multiply-adds / integer-multiply peak); the bound is the larger term.
     The integer peak is the measured v_mad_u64_u32 rate when given; a field
     product counts macs_per_mulmod 32x32 multiply-adds (136 for BN254's
-    8-limb Montgomery product, 4 for a Goldilocks 64 x 64 product)."""
+    8-limb Montgomery product, 4 for a Goldilocks 64 x 64 product). With
+    stream_gbs (the measured rate of a folding round's access pattern alone,
+    gkr_ubench kind 5) the HBM rate is also given as a fraction of it."""
     name, e = max(prof.items(), key=lambda kv: kv[1]["ms"])
     sec = e["ms"] / 1e3
     gbs = e["bytes"] / sec / 1e9
@@ -163,6 +168,9 @@ def roofline(prof, workload=None, mac_peak_tops=None, macs_per_mulmod=MACS_PER_M
              else "theoretical full-rate VALU"}
     r["alu_frac"] = round(tops / alu_peak, 4)
     r["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+    if stream_gbs:
+        r["hbm_stream_gbs"] = round(stream_gbs, 1)
+        r["hbm_frac_of_stream"] = round(gbs / stream_gbs, 4)
     r.update({"kernel": name, "launches_per_step": e["launches"],
               "avg_launch_us": round(e["ms"] * 1e3 / max(1, e["launches"]), 2),
               "hbm_gbs": round(gbs, 1), "alu_tops": round(tops, 3),
@@ -649,7 +657,8 @@ def main():
     if not args.no_profile:
         log("%s: profile pass (HIP events per launch)" % args.workload)
         prof = profile_pass(gkr, prover, d_in, spec.seed, args.profile_steps)
-        line["roofline"] = roofline(prof, args.workload, peaks["mad_u64_u32_per_s"] / 1e12)
+        line["roofline"] = roofline(prof, args.workload, peaks["mad_u64_u32_per_s"] / 1e12,
+                                    stream_gbs=peaks["round_stream_bytes_per_s"] / 1e9)
         line["kernel_classes"] = class_fractions(prof, peaks["mad_u64_u32_per_s"] / 1e12,
                                                  peaks.get("field_products_per_s"))
         line["kernels"] = {k: {"ms": round(v["ms"], 4), "launches": v["launches"]} for k, v in

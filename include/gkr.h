@@ -417,16 +417,20 @@ int32_t gkr_profile_enable(int32_t on);
 int32_t gkr_profile_read(gkr_profile_entry* out, uint32_t cap, uint32_t* count);
 
 /*
- * Integer-multiply microbenchmark of the device's vector ALU (this library's
- * own, for the roofline of the field-arithmetic kernels; no passage). Runs
+ * Microbenchmarks of the device's vector ALU and HBM (this library's own,
+ * for the roofline of the prover's kernels; no passage). Runs
  * one timed launch of `iters` iterations over every compute unit on the
  * current device and writes the grid-wide rate to *ops_per_s (and the
  * launch time to *ms, if not null). kind: 0 = v_mad_u64_u32 (32x32+64 ->
  * 64), 1 = v_mad_u64_u32 with its carry into an overflow word (the
  * multiply-accumulate of the field product, one operation per pair),
  * 2 = v_add_u32 (full-rate reference), 3 = v_mul_lo_u32 / v_mul_hi_u32,
- * 4 = Montgomery field products (the prover's device product). Allocates
- * and synchronises (not for timed or captured regions). Errors: GKR_EINVAL,
+ * 4 = Montgomery field products (the prover's device product), 5 = the HBM
+ * access pattern of a folding round without its arithmetic (per pair b < h =
+ * 2^24: read 32-byte entries b, b+h, b+2h, b+3h of a 2 GiB table, write
+ * entries b, b+h of a 1 GiB one; `iters` passes; *ops_per_s is then bytes
+ * moved per second, reads plus writes). Allocates (kind 5: 3 GiB) and
+ * synchronises (not for timed or captured regions). Errors: GKR_EINVAL,
  * GKR_ENOMEM, GKR_EDEVICE.
  */
 int32_t gkr_ubench(uint32_t kind, uint32_t iters, double* ops_per_s, double* ms);

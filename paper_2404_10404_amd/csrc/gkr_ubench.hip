@@ -1,5 +1,6 @@
-// Integer-multiply microbenchmarks of the VALU: the measured peaks the
-// roofline of the field-arithmetic kernels is taken against.
+// Integer-multiply microbenchmarks of the VALU, and the HBM stream of a
+// folding round: the measured ceilings the roofline of the prover's kernels
+// is read against (beside the datasheet peaks).
 //
 // Each kernel runs `iters` iterations of independent dependency chains per
 // thread (enough chains that the issue rate, not the latency, bounds them)
@@ -128,13 +129,75 @@ __global__ void __launch_bounds__(kUbBlock) k_ub_frmul(uint32_t iters, uint32_t*
   out[t] = s;
 }
 
+// The HBM access pattern of a folding round, without its arithmetic: for
+// each b < h, the 32-byte entries b, b + 2h, b + h and b + 3h of a 4h-entry
+// table are read and two 32-byte entries b and b + h of a 2h-entry table
+// written (as 16-byte global loads and stores, one pair per thread). The rate
+// it reaches is the practical ceiling of the round kernels' traffic.
+typedef uint32_t UbU4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) UbU4 UbGlobalU4;
+__global__ void __launch_bounds__(kUbBlock) k_ub_stream(const UbU4* src_g, UbU4* dst_g, uint64_t h) {
+  const uint64_t b = (uint64_t)blockIdx.x * kUbBlock + threadIdx.x;
+  if (b >= h) return;
+  const UbGlobalU4* src = (const UbGlobalU4*)src_g;
+  UbGlobalU4* dst = (UbGlobalU4*)dst_g;
+  const UbU4 a0 = src[2 * b], a1 = src[2 * b + 1];
+  const UbU4 c0 = src[2 * (b + 2 * h)], c1 = src[2 * (b + 2 * h) + 1];
+  const UbU4 e0 = src[2 * (b + h)], e1 = src[2 * (b + h) + 1];
+  const UbU4 f0 = src[2 * (b + 3 * h)], f1 = src[2 * (b + 3 * h) + 1];
+  dst[2 * b] = a0 ^ c0;
+  dst[2 * b + 1] = a1 ^ c1;
+  dst[2 * (b + h)] = e0 ^ f0;
+  dst[2 * (b + h) + 1] = e1 ^ f1;
+}
+constexpr uint64_t kUbStreamPairs = 1ull << 24;  // h: a 2 GiB source, a 1 GiB destination
+
+// Passes of the stream pattern: bytes moved per second (reads + writes).
+static int32_t ubench_stream(uint32_t passes, double* bytes_per_s, double* ms_out) {
+  const uint64_t h = kUbStreamPairs;
+  void *src = nullptr, *dst = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int32_t rc = GKR_OK;
+  if (hipMalloc(&src, 4 * h * 32) != hipSuccess || hipMalloc(&dst, 2 * h * 32) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("gkr_ubench: allocation failed");
+    rc = GKR_ENOMEM;
+  }
+  float ms = 0.f;
+  if (rc == GKR_OK && (hipMemset(src, 0x5a, 4 * h * 32) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+                       hipEventCreate(&e1) != hipSuccess))
+    rc = GKR_EDEVICE;
+  const uint32_t blocks = (uint32_t)(h / kUbBlock);
+  if (rc == GKR_OK) {
+    const UbU4* s = static_cast<const UbU4*>(src);
+    UbU4* d = static_cast<UbU4*>(dst);
+    k_ub_stream<<<blocks, kUbBlock>>>(s, d, h);  // warm-up
+    hipEventRecord(e0, nullptr);
+    for (uint32_t i = 0; i < passes; ++i) k_ub_stream<<<blocks, kUbBlock>>>(s, d, h);
+    hipEventRecord(e1, nullptr);
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = GKR_EDEVICE;
+  }
+  if (rc == GKR_EDEVICE) {
+    (void)hipGetLastError();
+    set_error("gkr_ubench: launch or timing failed");
+  } else if (rc == GKR_OK) {
+    *bytes_per_s = 6.0 * h * 32 * passes / (ms * 1e-3);
+    if (ms_out) *ms_out = ms;
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (src) hipFree(src);
+  if (dst) hipFree(dst);
+  return rc;
+}
+
 }  // namespace gkr
 
 using namespace gkr;
 
 extern "C" int32_t gkr_ubench(uint32_t kind, uint32_t iters, double* ops_per_s, double* ms_out) {
-  if (!ops_per_s || iters == 0 || kind > 4) {
-    set_error("gkr_ubench: kind must be 0..4, iters > 0, ops_per_s non-null");
+  if (!ops_per_s || iters == 0 || kind > 5) {
+    set_error("gkr_ubench: kind must be 0..5, iters > 0, ops_per_s non-null");
     return GKR_EINVAL;
   }
   int dev = 0, cus = 0;
@@ -144,6 +207,7 @@ extern "C" int32_t gkr_ubench(uint32_t kind, uint32_t iters, double* ops_per_s, 
     set_error("gkr_ubench: no HIP device");
     return GKR_EDEVICE;
   }
+  if (kind == 5) return ubench_stream(iters, ops_per_s, ms_out);
   const uint32_t blocks = (uint32_t)cus * 16;  // 16 waves per SIMD-quad: four per SIMD
   uint32_t* out = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;

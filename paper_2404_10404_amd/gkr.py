@@ -560,7 +560,8 @@ def set_contraction(matrix_cores: bool):
 
 
 UBENCH_KINDS = {0: "v_mad_u64_u32", 1: "v_mad_u64_u32 + v_addc (field multiply-accumulate)",
-                2: "v_add_u32", 3: "v_mul_lo_u32 / v_mul_hi_u32", 4: "Montgomery field product"}
+                2: "v_add_u32", 3: "v_mul_lo_u32 / v_mul_hi_u32", 4: "Montgomery field product",
+                5: "HBM stream of a folding round (bytes/s)"}
 
 
 def ubench(kind: int, iters: int = 2048) -> Tuple[float, float]:

@@ -135,6 +135,14 @@ def test_contraction_mode_round_trip_and_range():
     assert L.gkr_get_contraction(ctypes.byref(mode)) == 0 and mode.value == 1
 
 
+def test_ubench_rejects_unknown_kind():
+    import ctypes
+    L = gkr.lib()
+    rate, ms = ctypes.c_double(0), ctypes.c_double(0)
+    assert L.gkr_ubench(6, 1, ctypes.byref(rate), ctypes.byref(ms)) == -1  # GKR_EINVAL, before any device call
+    assert L.gkr_ubench(5, 0, ctypes.byref(rate), ctypes.byref(ms)) == -1
+
+
 def test_build_refuses_register_spills():
     """The build reads the compiler's resource-usage remarks and refuses a
     kernel that spills vector registers to scratch memory."""
