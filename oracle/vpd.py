@@ -5,12 +5,12 @@ verifier has the prover commit to V_D~ before the GKR protocol runs; when the
 last layer leaves two claims V_D~(r_x) = v_x and V_D~(r_y) = v_y, the prover
 opens the commitment at those two points. Virgo's commitment (a verifiable
 polynomial delegation) is transparent and built on the univariate sumcheck;
-the paper gives no more detail. This module is the oracle of this build's
+the paper gives no more detail. This module is the oracle of this project's
 reading of it:
 
   polynomial   the N = 2^s inputs are the coefficients of f(X) = sum_b V[b] X^b.
   claim        with w[b] = eq(r1, b) + lam eq(r2, b) (variable 1 = the most
-               significant bit of b, as everywhere in this build) the two claims
+               significant bit of b, as everywhere in this project) the two claims
                become c = c1 + lam c2 = sum_b V[b] w[b].
   tensor       sum_b eq(r, b) Y^b = prod_j ((1 - r_j) + r_j Y^(2^(s-j))) =: Q_r(Y),
                Q = Q_r1 + lam Q_r2, evaluated in O(s) operations at any Y.
