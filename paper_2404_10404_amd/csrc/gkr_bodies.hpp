@@ -387,13 +387,24 @@ __device__ __forceinline__ void phase1_entry(const Step& st, uint64_t e, Fr& g, 
   const Fr cu = ldf(P<const Fr*>(st, 7), c), cv = ldf(P<const Fr*>(st, 8), c);
   g = fr_zero();
   h = fr_zero();
-  const uint32_t k1 = xrow[x + 1];
-  for (uint32_t k = xrow[x]; k < k1; ++k) {
+  // The first gate's terms are assigned, not added to zero: with 2^n >= 64
+  // copies every lane of a wave walks the same gate list (the entries of one
+  // x), so these branches do not diverge and an entry with one gate costs no
+  // additions.
+  const uint32_t k0 = xrow[x], k1 = xrow[x + 1];
+  for (uint32_t k = k0; k < k1; ++k) {
     const uint2 ent = xent[k];
     const uint64_t z = ent.x, y = ent.y & 0x7fffffffu;
     const Fr T = fr_mul_add2(ldf(aU, z), cu, ldf(bV, z), cv);
     const Fr tw = fr_mul(T, ldf(W, (y << n) | c));
-    if (ent.y >> 31) {
+    if (k == k0) {
+      if (ent.y >> 31) {
+        g = tw;
+      } else {
+        g = T;
+        h = tw;
+      }
+    } else if (ent.y >> 31) {
       g = fr_add(g, tw);
     } else {
       g = fr_add(g, T);

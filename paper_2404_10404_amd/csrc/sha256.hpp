@@ -21,6 +21,15 @@ GKR_HD uint32_t xor3_32(uint32_t a, uint32_t b, uint32_t c) {
   return a ^ b ^ c;
 #endif
 }
+// Majority of a, b, c: one three-input bit operation on gfx950 (truth table
+// 0xE8: set where at least two inputs are).
+GKR_HD uint32_t maj32(uint32_t a, uint32_t b, uint32_t c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
+#else
+  return (a & b) ^ (a & c) ^ (b & c);
+#endif
+}
 GKR_HD uint32_t bswap32(uint32_t x) {
   return (x >> 24) | ((x >> 8) & 0xff00u) | ((x << 8) & 0xff0000u) | (x << 24);
 }
@@ -87,7 +96,7 @@ GKR_HD Sha256State sha256_compress_v(Sha256State st, Sha256Block blk) {
       const uint32_t ch = (e & f) ^ (~e & g);
       const uint32_t t1 = h + S1 + ch + kSha256K[j + i] + wi;
       const uint32_t S0 = xor3_32(rotr32(a, 2), rotr32(a, 13), rotr32(a, 22));
-      const uint32_t maj = (a & b) ^ (a & c) ^ (b & c);
+      const uint32_t maj = maj32(a, b, c);
       const uint32_t t2 = S0 + maj;
       h = g; g = f; f = e; e = d + t1;
       d = c; c = b; b = a; a = t1 + t2;
